@@ -1,0 +1,173 @@
+"""Exhaustive tree search with the BCTS correction, FP64 (test infrastructure
+only).
+
+What is computed (and where the paper defines it):
+
+* the d-step value Q_d(s, a) = max over a_1..a_{d-1} and the leaf action a_d
+  of  sum_{t<d} gamma^t r_t + gamma^d Q(s_d, a_d),  with s_0 = s, a_0 = a
+  (Eq. 1) -- here by plain recursive depth-first search, the non-parallel
+  search the paper compares Batch-BFS against (Sec. 4.1);
+* the root network values Q_0 = Q(s_0, .) and pi_o = argmax Q_0 (Sec. 3.2);
+* the Bellman errors at depth 0/1: delta(a) = r(s_0, a) + gamma max_a'
+  Q(s_1^a, a') - Q(s_0, a) (Prop. 3.6 and the paragraph after it);
+* the penalty B(d_e, d_o, A, d) = sqrt(log A) (d_e sqrt(d) - d_o sqrt(d-1))
+  - (d_e - d_o) / sqrt(8) (Eq. 6), with d_o = |delta(pi_o)| and d_e the mean
+  of |delta(a)| over a != pi_o;
+* the corrected root vector: Q_d(s, a) - c gamma^d B for a != pi_o, and
+  Q_d(s, pi_o) unchanged (Eq. 3, with B in place of B_e - B_o and the
+  constant multiplier c of Sec. 5.1); the action is its argmax (Eq. 4),
+  lowest index on ties.
+
+Readings where the paper is silent: the log is natural; delta enters through
+its magnitude; depth 0 applies no correction (the pre-trained agent itself);
+depth 1 uses Eq. 6 as written.
+
+``enumerate_nodes`` lists every tree node in the index order of Alg. 1: the
+child of node j by action a has index j*A + a, so the root action of leaf i is
+floor(i / A^(d-1)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import env as E
+from . import qnet as Q
+
+TIE_REL = 1e-6
+
+
+@dataclass
+class World:
+    delta: np.ndarray   # int [18][2]
+    vel: np.ndarray     # int [7][2]
+    w64: dict           # FP64 Q-network weights (qnet.prepare)
+
+
+def qmax(world: World, stacks: np.ndarray, A: int) -> np.ndarray:
+    """max_a Q(s, a) for a batch of stacks."""
+    return Q.qvalues(stacks, world.w64, A).max(axis=1)
+
+
+def children(world: World, pos, stack, A: int):
+    return [E.step(pos, stack, a, world.delta, world.vel) for a in range(A)]
+
+
+def dfs(world: World, pos, stack, k: int, d: int, A: int, gamma: float) -> float:
+    """Value of a node at level k < d: max_a [ r_a + gamma * value(child_a) ],
+    where a node at level d is worth max_a Q(s, a)."""
+    kids = children(world, pos, stack, A)
+    if k + 1 == d:
+        v = qmax(world, np.stack([s for _, s, _ in kids]), A)
+        return max(r + gamma * float(v[a]) for a, (_, _, r) in enumerate(kids))
+    return max(r + gamma * dfs(world, p, s, k + 1, d, A, gamma) for p, s, r in kids)
+
+
+def root_values(world: World, pos, stack, d: int, A: int, gamma: float) -> np.ndarray:
+    """Q_d(s_0, a) for every root action a (Eq. 1); d >= 1."""
+    assert d >= 1
+    out = np.empty(A)
+    for a, (p, s, r) in enumerate(children(world, pos, stack, A)):
+        if d == 1:
+            out[a] = r + gamma * float(qmax(world, s[None], A)[0])
+        else:
+            out[a] = r + gamma * dfs(world, p, s, 1, d, A, gamma)
+    return out
+
+
+def penalty(de: float, do: float, A: int, d: int) -> float:
+    """B of Eq. 6 (natural log)."""
+    return math.sqrt(math.log(A)) * (de * math.sqrt(d) - do * math.sqrt(d - 1)) - (de - do) / math.sqrt(8.0)
+
+
+def argmax_low(v) -> int:
+    v = np.asarray(v)
+    return int(np.flatnonzero(v == v.max())[0])
+
+
+def tie_set(v, rel: float = TIE_REL) -> list[int]:
+    v = np.asarray(v, dtype=np.float64)
+    m = float(v.max())
+    return [int(a) for a in np.flatnonzero(v >= m - rel * max(1.0, abs(m)))]
+
+
+@dataclass
+class Result:
+    action: int
+    q: np.ndarray                       # the returned root vector
+    q_d: np.ndarray | None = None       # uncorrected d-step values
+    q0: np.ndarray | None = None
+    pi_o: int | None = None
+    delta: np.ndarray | None = None
+    B: float | None = None
+    ties: list = field(default_factory=list)
+
+
+def search(world: World, pos, stack, d: int, A: int, gamma: float,
+           correction: bool = True, c: float = 1.0, mode: str = "eq6") -> Result:
+    """One root: the returned vector and action of the corrected search.
+    mode "eq6" uses B of Eq. 6; mode "gev" uses the exact bias gap of
+    Lemma 3.2 with sigma = |delta| / sqrt(2)."""
+    q0 = Q.qvalues(stack, world.w64, A)
+    if d == 0:
+        return Result(action=argmax_low(q0), q=q0.copy(), q0=q0, ties=tie_set(q0))
+    qd = root_values(world, pos, stack, d, A, gamma)
+    if not correction:
+        return Result(action=argmax_low(qd), q=qd.copy(), q_d=qd, ties=tie_set(qd))
+    pi_o = argmax_low(q0)
+    delta = np.empty(A)
+    for a, (p, s, r) in enumerate(children(world, pos, stack, A)):
+        delta[a] = r + gamma * float(qmax(world, s[None], A)[0]) - q0[a]
+    do = abs(delta[pi_o])
+    de = float(np.mean([abs(delta[a]) for a in range(A) if a != pi_o]))
+    if mode == "eq6":
+        B = penalty(de, do, A, d)
+    else:
+        from . import gev
+        B = gev.exact_gap(de / math.sqrt(2.0), do / math.sqrt(2.0), A, d)
+    q = qd.copy()
+    for a in range(A):
+        if a != pi_o:
+            q[a] = qd[a] - c * gamma ** d * B
+    return Result(action=argmax_low(q), q=q, q_d=qd, q0=q0, pi_o=pi_o, delta=delta, B=B,
+                  ties=tie_set(q))
+
+
+def enumerate_nodes(world: World, pos, stack, d: int, A: int):
+    """Per level k = 1..d: positions [A^k][8][2], frames [A^k][84][84] and
+    rewards [A^k], node index = parent index * A + action."""
+    levels = []
+    cur = [(np.asarray(pos, dtype=np.int64), np.asarray(stack))]
+    for _ in range(d):
+        nxt, P, F, R = [], [], [], []
+        for p, s in cur:
+            for a in range(A):
+                p2, s2, r = E.step(p, s, a, world.delta, world.vel)
+                nxt.append((p2, s2))
+                P.append(p2)
+                F.append(s2[-1])
+                R.append(r)
+        levels.append((np.array(P, dtype=np.int32), np.array(F, dtype=np.uint8),
+                       np.array(R, dtype=np.int32)))
+        cur = nxt
+    return levels
+
+
+def node_path(i: int, k: int, A: int) -> list[int]:
+    """Actions (a_0..a_{k-1}) leading to node i of level k."""
+    acts = []
+    for _ in range(k):
+        acts.append(i % A)
+        i //= A
+    return acts[::-1]
+
+
+def node_at(world: World, pos, stack, acts):
+    """Walk an action sequence from the root: (positions, stack, rewards)."""
+    p, s, rs = np.asarray(pos, dtype=np.int64), np.asarray(stack), []
+    for a in acts:
+        p, s, r = E.step(p, s, a, world.delta, world.vel)
+        rs.append(r)
+    return p, s, rs
