@@ -1,0 +1,213 @@
+/*
+ * bcts.h -- C ABI of libbcts: Batch-BFS exhaustive tree search with the
+ * Bellman-corrected (BCTS) root correction, on one AMD MI355X (gfx950).
+ *
+ * What a search computes, per root state s_0 with A actions and depth d:
+ *
+ *   Q_d(s_0, a) = max over a_1..a_{d-1}, a_d of
+ *                 sum_{t<d} gamma^t r_t + gamma^d Q(s_d, a_d)         (Eq. 1)
+ *
+ * evaluated level by level: every node of depth k is expanded for all A
+ * actions at once, the A^d leaves are scored by the Q-network, and returns
+ * are backed up with the child index j*A + a so that the root action of leaf
+ * i is floor(i / A^(d-1)) (Alg. 1).  The root vector is then corrected for
+ * the off-policy bias of the maximum (Eq. 3 with the penalty B of Eq. 6):
+ *
+ *   pi_o      = argmax_a Q(s_0, a)                      (network at the root)
+ *   delta(a)  = r(s_0, a) + gamma max_a' Q(s_1^a, a') - Q(s_0, a)  (Prop. 3.6)
+ *   d_o       = |delta(pi_o)|,  d_e = mean_{a != pi_o} |delta(a)|
+ *   B         = sqrt(ln A) (d_e sqrt(d) - d_o sqrt(d-1)) - (d_e - d_o)/sqrt(8)
+ *   Q^BCTS(a) = Q_d(s_0, a) - c gamma^d B   for a != pi_o,
+ *               Q_d(s_0, pi_o)              for a == pi_o
+ *   action    = argmax_a Q^BCTS(a)  (lowest index on ties)          (Eq. 4)
+ *
+ * c is the constant multiplier of the correction (Sec. 5.1).  Depth 0 returns
+ * Q(s_0, .) itself; a search without correction returns Q_d.  With
+ * BCTS_CORR_EXACT_GEV the penalty is instead the exact gap of Lemma 3.2,
+ * sigma_e Bn(A^d - A^(d-1)) - sigma_o Bn(A^(d-1)) with sigma = |delta|/sqrt 2.
+ *
+ * The forward model is a deterministic sprite world with Atari-shaped state
+ * (84x84 uint8 frames, a stack of 4, channel 0 oldest); the value network is
+ * the Nature-DQN CNN.  See bcts_set_env and bcts_set_qnet.
+ *
+ * Conventions for every entry point:
+ *  - Host pointers are owned by the caller; the library copies what it needs
+ *    before returning and keeps no caller pointer.  Device pointers (the
+ *    *_device entry points) are borrowed until the work enqueued on the given
+ *    stream completes.
+ *  - The context owns all device memory, streams and graphs.  A context is
+ *    not thread-safe: calls on one context must not overlap.
+ *  - Arguments are validated before any GPU work; an invalid call returns
+ *    BCTS_E_INVAL (or BCTS_E_STATE) and leaves the context usable.  A HIP
+ *    failure returns BCTS_E_HIP and puts the context in an error state in
+ *    which every call but bcts_last_error, bcts_reset and bcts_destroy
+ *    returns BCTS_E_STATE.  bcts_last_error describes the latest failure.
+ */
+#ifndef BCTS_H
+#define BCTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BCTS_FRAME      84          /* frame side (pixels)                      */
+#define BCTS_FRAME_BYTES (84 * 84)  /* one uint8 frame                          */
+#define BCTS_STACK      4           /* frames per state, channel 0 oldest       */
+#define BCTS_SPRITES    8           /* sprite 0 is the agent                    */
+#define BCTS_MAX_A      18          /* Atari's full action set                  */
+#define BCTS_MAX_DEPTH  6
+/* FP32 Q-network blob length: conv1.w[32][4][8][8], conv1.b[32],
+ * conv2.w[64][32][4][4], conv2.b[64], conv3.w[64][64][3][3], conv3.b[64],
+ * fc1.w[512][3136] (input index c*49 + h*7 + w), fc1.b[512], fc2.w[18][512],
+ * fc2.b[18] -- PyTorch's OIHW / [out][in] layouts, in this order.           */
+#define BCTS_QNET_NUMEL 1693362
+
+typedef enum {
+  BCTS_OK = 0,
+  BCTS_E_INVAL = -1,   /* bad argument; nothing was launched                 */
+  BCTS_E_NOMEM = -2,   /* over the context's HBM budget / allocation failed  */
+  BCTS_E_HIP = -3,     /* HIP runtime error; context is now in error state   */
+  BCTS_E_BUSY = -4,    /* serving: the ticket is not finished yet            */
+  BCTS_E_STATE = -5    /* missing env/qnet, unknown ticket, or error state   */
+} bcts_status;
+
+typedef enum {
+  BCTS_FP32 = 0,       /* FP32 operands, FP32 accumulate                      */
+  BCTS_BF16 = 1,       /* BF16 operands and activations, FP32 accumulate      */
+  BCTS_FP8 = 2         /* OCP e4m3 operands with per-layer scales, FP32 acc.  */
+} bcts_precision;
+
+typedef enum {
+  BCTS_CORR_EQ6 = 0,        /* penalty B of Eq. 6                             */
+  BCTS_CORR_EXACT_GEV = 1   /* exact bias gap of Lemma 3.2                    */
+} bcts_corr_mode;
+
+/* Sprite-world dynamics: action a moves sprite 0 by delta[a] = (dx, dy);
+ * sprite i >= 1 moves by vel[i-1] every step; coordinates wrap modulo 84.
+ * Each step renders an 84x84 frame: 6x6 squares anchored at (x, y) extending
+ * +5 in x and y with wrap, value 128 for sprites 1..7 and 255 for sprite 0
+ * (max compositing), and scores the number of sprites 1..7 whose square
+ * overlaps sprite 0's (circular distance < 6 in x and in y), after the move. */
+typedef struct {
+  int32_t delta[BCTS_MAX_A][2];
+  int32_t vel[BCTS_SPRITES - 1][2];
+} bcts_env_params;
+
+/* Root correction (Eq. 3).  enabled = 0 returns the uncorrected Q_d;
+ * scale is the constant c; mode selects the penalty.                       */
+typedef struct {
+  int32_t enabled;
+  float scale;
+  int32_t mode;
+} bcts_correction;
+
+typedef struct bcts_ctx bcts_ctx;
+
+/* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * device memory the context may hold (0 = 80% of the device's free memory).
+ * BCTS_E_HIP if the device cannot be used.                                 */
+bcts_status bcts_create(int hip_device, size_t hbm_budget_bytes, bcts_ctx** out);
+void bcts_destroy(bcts_ctx* ctx);
+/* Text of the last failure on ctx ("" if none); valid until the next call. */
+const char* bcts_last_error(const bcts_ctx* ctx);
+/* Leave the error state: synchronises, drops pending serving work (those
+ * tickets then poll BCTS_E_STATE) and releases the work arena.             */
+bcts_status bcts_reset(bcts_ctx* ctx);
+
+/* Environment tables (copied).  |delta| <= 3 and |vel| <= 2 per component. */
+bcts_status bcts_set_env(bcts_ctx* ctx, const bcts_env_params* env);
+
+/* Q-network weights: FP32 blob of BCTS_QNET_NUMEL floats (layout above),
+ * copied and converted on the device for every precision.  A search with A
+ * actions uses fc2 rows 0..A-1.  Resets FP8 scales to their calibration
+ * default (see bcts_calibrate_fp8).                                         */
+bcts_status bcts_set_qnet(bcts_ctx* ctx, const float* blob, size_t n_floats);
+/* Precision of the Q-network for subsequent searches (default BCTS_FP32).  */
+bcts_status bcts_set_precision(bcts_ctx* ctx, bcts_precision prec);
+/* FP8: derive per-layer activation scales from the FP32 network's
+ * activation maxima on n calibration stacks (host uint8 [n][4][84][84]),
+ * so that each layer's input maps to the e4m3 range.  The scales are kept
+ * until the next bcts_set_qnet; bcts_get_fp8_scales reads them (5 floats).  */
+bcts_status bcts_calibrate_fp8(bcts_ctx* ctx, int32_t n, const uint8_t* stacks);
+bcts_status bcts_get_fp8_scales(bcts_ctx* ctx, float* out5);
+bcts_status bcts_set_fp8_scales(bcts_ctx* ctx, const float* in5);
+
+/* Search n_roots roots that share (depth, A).  Host buffers:
+ *   pos     int32 [n][8][2]   (x, y) in [0, 84)
+ *   stacks  uint8 [n][4][84][84]
+ *   out_action int32 [n], out_q float [n][A] (the corrected vector).
+ * depth in [0, 6], A in [1, 18] (A >= 2 when the correction is enabled and
+ * depth >= 1), gamma in (0, 1].                                             */
+bcts_status bcts_search(bcts_ctx* ctx, int32_t n_roots, const int32_t* pos, const uint8_t* stacks,
+                        int32_t depth, int32_t A, float gamma, bcts_correction corr,
+                        int32_t* out_action, float* out_q);
+
+/* Search n_roots roots of individual depth[i] and A[i] in one batch (host
+ * buffers).  out_q is float [n][18]; row i holds root i's vector in entries
+ * 0..A[i]-1 and -INFINITY after.                                            */
+bcts_status bcts_search_batch(bcts_ctx* ctx, int32_t n_roots, const int32_t* pos,
+                              const uint8_t* stacks, const int32_t* depth, const int32_t* A,
+                              float gamma, bcts_correction corr, int32_t* out_action,
+                              float* out_q);
+
+/* As bcts_search_batch, but pos/stacks/out_action/out_q are DEVICE pointers
+ * and the work is enqueued on `hip_stream` (a hipStream_t; NULL = the
+ * context's stream) without a host synchronisation.  depth and A stay host
+ * arrays (the plan is made on the host).  Positions are not range-checked
+ * here (they are device data); out-of-range positions are wrapped modulo 84. */
+bcts_status bcts_search_batch_device(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos,
+                                     const uint8_t* d_stacks, const int32_t* depth,
+                                     const int32_t* A, float gamma, bcts_correction corr,
+                                     int32_t* d_out_action, float* d_out_q, void* hip_stream);
+
+/* Capture the device search of one batch shape into a HIP graph and replay
+ * it `replays` times (buffers as in bcts_search_batch_device, stream NULL =
+ * context stream).  Results of every replay equal the eager search.        */
+bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos,
+                                    const uint8_t* d_stacks, const int32_t* depth,
+                                    const int32_t* A, float gamma, bcts_correction corr,
+                                    int32_t* d_out_action, float* d_out_q, int32_t replays,
+                                    void* hip_stream);
+
+/* ---- serving: continuous batching with HBM-budget admission ------------ */
+/* Queue one request (host buffers copied).  Returns a ticket.  Requests
+ * whose own minimal footprint exceeds the budget fail with BCTS_E_NOMEM.   */
+bcts_status bcts_submit(bcts_ctx* ctx, const int32_t* pos, const uint8_t* stack, int32_t depth,
+                        int32_t A, float gamma, bcts_correction corr, uint64_t* ticket);
+/* Advance the engine without blocking: retire finished batches, admit
+ * queued requests in arrival order while the budget allows, launch them.
+ * Returns the number of requests still pending in *pending.               */
+bcts_status bcts_progress(bcts_ctx* ctx, int32_t* pending);
+/* Result of a ticket: BCTS_OK (copied out, ticket released), BCTS_E_BUSY
+ * (not finished), BCTS_E_STATE (unknown ticket).  q has room for A floats;
+ * t_done is the host monotonic time (s) at which completion was observed.  */
+bcts_status bcts_poll(bcts_ctx* ctx, uint64_t ticket, int32_t* action, float* q, double* t_done);
+/* Serving limits: max requests per engine batch, max batches in flight.   */
+bcts_status bcts_serve_config(bcts_ctx* ctx, int32_t max_batch, int32_t max_inflight);
+/* Device bytes one request of (depth, A) reserves while admitted.         */
+size_t bcts_request_bytes(int32_t depth, int32_t A);
+
+/* ---- parity / debug exports (not on the timed path) -------------------- */
+/* Expand one root to `depth` and copy every node out in the index order of
+ * Alg. 1 (level 1 first; node j*A + a is child a of node j).  Host outputs
+ * sized sum_{k=1..depth} A^k: out_pos int32 [..][8][2], out_frames uint8
+ * [..][84][84], out_reward int32 [..].                                      */
+bcts_status bcts_debug_expand(bcts_ctx* ctx, const int32_t* pos, const uint8_t* stack,
+                              int32_t depth, int32_t A, int32_t* out_pos, uint8_t* out_frames,
+                              int32_t* out_reward);
+/* Q-network on n host stacks at the current precision: out_q float [n][A]. */
+bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
+                            float* out_q);
+/* Average duration (ms) of each stage kernel over the last search on ctx:
+ * out[0] expansion, out[1] leaf Q-network, out[2] backup + correction,
+ * out[3] whole search; measured with HIP events when timing is enabled.    */
+bcts_status bcts_set_timing(bcts_ctx* ctx, int32_t enabled);
+bcts_status bcts_get_timing(bcts_ctx* ctx, double* out4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCTS_H */

@@ -29,6 +29,62 @@ def relu(x: np.ndarray) -> np.ndarray:
     return np.maximum(x, 0.0)
 
 
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (nearest even) and back; torch's conversion."""
+    import torch
+    return torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).double().numpy()
+
+
+def round_e4m3(x: np.ndarray) -> np.ndarray:
+    """Saturate to +-448 and round to OCP FP8 e4m3 (nearest even) and back;
+    torch's float8_e4m3fn conversion."""
+    import torch
+    y = np.clip(np.asarray(x, dtype=np.float64), -448.0, 448.0).astype(np.float32)
+    return torch.from_numpy(y).to(torch.float8_e4m3fn).double().numpy()
+
+
+def qvalues_lowp(stacks: np.ndarray, w: dict, A: int, prec: str, ascale=None) -> np.ndarray:
+    """Q-values with each layer's two operands rounded to a low precision and
+    the products summed in FP64 (the emulation a BF16/FP8 matrix-core path is
+    compared against).
+
+    bf16: pixels (integers, exact) and weights rounded to bf16; every later
+          layer input rounded to bf16; 1/255 applied after conv1's sum.
+    fp8:  layer l's input x and weights W enter as e4m3(x * ascale[l]) and
+          e4m3(W * wscale[l]) with wscale[l] = 448 / max|W_l|; the sum is
+          divided by ascale[l] * wscale[l] (and 255 for conv1).
+    Biases stay exact; ReLU after every layer but the last."""
+    one = stacks.ndim == 3
+    s = stacks[None] if one else stacks
+    layers = (("conv1", 4), ("conv2", 2), ("conv3", 1), ("fc1", 0), ("fc2", 0))
+    x = s.astype(np.float64)                     # raw pixels
+    for l, (name, stride) in enumerate(layers):
+        W = w[name + ".w"]
+        b = w[name + ".b"]
+        if name == "fc2":
+            W, b = W[:A], b[:A]
+        if prec == "bf16":
+            xq, Wq, div = round_bf16(x), round_bf16(W), 1.0
+        elif prec == "fp8":
+            ws = 448.0 / float(np.abs(w[name + ".w"]).max())
+            xq = round_e4m3(x * float(ascale[l]))
+            Wq = round_e4m3(W * ws)
+            div = float(ascale[l]) * ws
+        else:
+            raise ValueError(prec)
+        if l == 0:
+            div *= 255.0
+        if stride:
+            zero = np.zeros_like(b)
+            y = conv2d(xq, Wq, zero, stride) / div + b[None, :, None, None]
+        else:
+            if l == 3:
+                xq = xq.reshape(xq.shape[0], -1)
+            y = (xq @ Wq.T) / div + b
+        x = relu(y) if l < 4 else y
+    return x[0] if one else x
+
+
 def qvalues(stacks: np.ndarray, w: dict, A: int) -> np.ndarray:
     """Q-values [n][A] (FP64) for stacks uint8 [n][4][84][84] (or one stack);
     `w` is the output of prepare()."""

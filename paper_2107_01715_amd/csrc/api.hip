@@ -1,0 +1,1132 @@
+// C ABI of libbcts: context, argument validation, the search planner and the
+// launch sequence of a batched Batch-BFS search (Alg. 1 for many roots at
+// once, followed by the correction of Eq. 3).
+//
+// A search over n roots runs, on one stream:
+//   1. expand level k = 1..max depth      (one launch per level, all roots)
+//   2. Q-network over every eval item     (chunks of items, 5 launches each)
+//   3. backup + correction + argmax       (one launch, one wavefront per root)
+// The plan (node counts A^k per root, eval segments, arena offsets) is made on
+// the host; its tables are copied to the device once per search.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/bcts.h"
+#include "bcts_internal.h"
+
+using namespace bcts;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Eq. 6 penalty coefficients: B = pen_e d_e - pen_o d_o
+void eq6_coeffs(int A, int d, double* pe, double* po) {
+  const double s = std::sqrt(std::log((double)A)), r8 = 1.0 / std::sqrt(8.0);
+  *pe = s * std::sqrt((double)d) - r8;
+  *po = s * std::sqrt((double)(d - 1)) - r8;
+}
+
+// z with Phi(z) = 1 - p (upper tail p <= 1/2), by bisection on
+// 0.5 erfc(z / sqrt 2) = p over [0, 40]; the tail function is monotone and
+// erfc keeps full relative accuracy far into the tail.
+double probit_upper_tail(double p) {
+  double lo = 0.0, hi = 40.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (0.5 * std::erfc(mid / std::sqrt(2.0)) > p) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Lemma 3.2: bias of the max of n Gaussians per unit sigma
+double gev_bias(double n) {
+  if (n <= 1.0) return 0.0;
+  const double g = 0.57721566490153286060651209;
+  return g * probit_upper_tail(1.0 / (M_E * n)) + (1.0 - g) * probit_upper_tail(1.0 / n);
+}
+
+// exact gap with sigma = |delta| / sqrt 2: B = pen_e d_e - pen_o d_o
+void gev_coeffs(int A, int d, double* pe, double* po) {
+  const double no = std::pow((double)A, d - 1), ne = std::pow((double)A, d) - no;
+  *pe = gev_bias(ne) / std::sqrt(2.0);
+  *po = gev_bias(no) / std::sqrt(2.0);
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct Plan {
+  int n = 0, maxd = 0;
+  std::vector<RootInfo> roots;
+  std::vector<Seg> segs;
+  long long n_items = 0;
+  long long lvl_count[kMaxD + 1] = {0};
+  std::vector<int> lvl_root[kMaxD + 1];
+  std::vector<long long> lvl_start[kMaxD + 1];
+  long long chunk = 0;
+  // arena offsets
+  size_t o_root_pos = 0, o_root_stack = 0, o_roots = 0, o_segs = 0, o_V = 0, o_q0 = 0,
+         o_desc = 0, o_ws = 0, o_act = 0, o_q = 0, total = 0;
+  size_t o_pos[kMaxD + 1] = {0}, o_frames[kMaxD + 1] = {0}, o_ret[kMaxD + 1] = {0},
+         o_rew[kMaxD + 1] = {0}, o_lroot[kMaxD + 1] = {0}, o_lstart[kMaxD + 1] = {0};
+  size_t table_bytes = 0;   // bytes of host tables uploaded (roots .. lstart)
+};
+
+struct bcts_ctx {
+  int device = 0;
+  size_t budget = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool error_state = false;
+  bool env_set = false, qnet_set = false;
+  EnvTables env{};
+  int prec = P_FP32;
+  long long chunk_items = 8192;
+  // weights
+  void* wmem = nullptr;
+  size_t wbytes = 0;
+  QnetDev q{};
+  float wabs[5] = {0};
+  bool fp8_calibrated = false;
+  // arena
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // pinned staging for tables and host I/O
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // timing
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double t_ms[4] = {0, 0, 0, 0};
+  // serving
+  struct ServeEngine* serve = nullptr;
+};
+
+namespace {
+
+bcts_status fail(bcts_ctx* c, bcts_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) {
+    c->err = buf;
+    if (st == BCTS_E_HIP) c->error_state = true;
+  }
+  return st;
+}
+
+#define HIPCHECK(ctx, expr)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, BCTS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+bcts_status check_usable(bcts_ctx* c) {
+  if (!c) return BCTS_E_INVAL;
+  if (c->error_state) return BCTS_E_STATE;
+  c->err.clear();
+  return BCTS_OK;
+}
+
+bcts_status ensure_pinned(bcts_ctx* c, size_t bytes) {
+  if (c->pinned_bytes >= bytes) return BCTS_OK;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (c->pinned) HIPCHECK(c, hipHostFree(c->pinned));
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  size_t nb = std::max(bytes, (size_t)1 << 20);
+  HIPCHECK(c, hipHostMalloc((void**)&c->pinned, nb, hipHostMallocDefault));
+  c->pinned_bytes = nb;
+  return BCTS_OK;
+}
+
+bcts_status ensure_arena(bcts_ctx* c, size_t bytes) {
+  if (c->arena_bytes >= bytes) return BCTS_OK;
+  if (bytes + c->wbytes > c->budget)
+    return fail(c, BCTS_E_NOMEM, "search needs %zu bytes of device memory; budget is %zu", bytes + c->wbytes,
+                c->budget);
+  // grow geometrically (bounded by the budget) to avoid re-allocation churn
+  size_t want = std::min(std::max(bytes, c->arena_bytes * 3 / 2), c->budget - c->wbytes);
+  if (want < bytes) want = bytes;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (c->arena) HIPCHECK(c, hipFree(c->arena));
+  c->arena = nullptr;
+  c->arena_bytes = 0;
+  hipError_t e = hipMalloc((void**)&c->arena, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, BCTS_E_NOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  c->arena_bytes = want;
+  return BCTS_OK;
+}
+
+bcts_status validate_shape(bcts_ctx* c, int A, int d, const bcts_correction& corr) {
+  if (A < 1 || A > kMaxA) return fail(c, BCTS_E_INVAL, "A=%d outside [1,18]", A);
+  if (d < 0 || d > kMaxD) return fail(c, BCTS_E_INVAL, "depth=%d outside [0,6]", d);
+  if (corr.enabled && d >= 1 && A < 2)
+    return fail(c, BCTS_E_INVAL, "the correction needs A >= 2 (there is no other action)");
+  return BCTS_OK;
+}
+
+bcts_status validate_common(bcts_ctx* c, int n, float gamma, const bcts_correction& corr) {
+  if (n <= 0) return fail(c, BCTS_E_INVAL, "n_roots=%d must be positive", n);
+  if (!(gamma > 0.f && gamma <= 1.f)) return fail(c, BCTS_E_INVAL, "gamma=%g outside (0,1]", gamma);
+  if (corr.enabled && !std::isfinite(corr.scale))
+    return fail(c, BCTS_E_INVAL, "correction scale is not finite");
+  if (corr.enabled && corr.mode != BCTS_CORR_EQ6 && corr.mode != BCTS_CORR_EXACT_GEV)
+    return fail(c, BCTS_E_INVAL, "unknown correction mode %d", corr.mode);
+  if (!c->env_set) return fail(c, BCTS_E_STATE, "no environment set (bcts_set_env)");
+  if (!c->qnet_set) return fail(c, BCTS_E_STATE, "no Q-network set (bcts_set_qnet)");
+  return BCTS_OK;
+}
+
+bcts_status validate_pos(bcts_ctx* c, int n, const int32_t* pos) {
+  for (long long i = 0; i < (long long)n * kSprites * 2; ++i)
+    if (pos[i] < 0 || pos[i] >= kFrame)
+      return fail(c, BCTS_E_INVAL, "root %lld: position %d outside [0,84)", i / (kSprites * 2), pos[i]);
+  return BCTS_OK;
+}
+
+// Build the plan: node counts, eval segments and the arena layout.
+// `q_stride` is the row stride of out_q; `qnet_only` makes every root a
+// single root-kind eval (debug Q-network on stacks).
+void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
+               const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
+               bool host_io) {
+  p = Plan();
+  p.n = n;
+  p.roots.resize(n);
+  for (int r = 0; r < n; ++r) p.maxd = std::max(p.maxd, (int)depth[r]);
+  // level node bases (root-major inside each level)
+  for (int r = 0; r < n; ++r) {
+    RootInfo& ri = p.roots[r];
+    std::memset(&ri, 0, sizeof ri);
+    ri.A = A[r];
+    ri.d = depth[r];
+    ri.gamma_d = (float)std::pow((double)gamma, (double)ri.d);
+    ri.corr = (corr.enabled && ri.d >= 1) ? 1 : 0;
+    ri.q_stride = q_stride;
+    long long cnt = 1;
+    for (int k = 1; k <= kMaxD; ++k) {
+      cnt *= ri.A;
+      if (k <= ri.d) {
+        ri.base[k] = p.lvl_count[k];
+        p.lvl_root[k].push_back(r);
+        p.lvl_start[k].push_back(p.lvl_count[k]);
+        p.lvl_count[k] += cnt;
+      } else {
+        ri.base[k] = -1;
+      }
+    }
+    if (ri.corr) {
+      double pe, po;
+      if (corr.mode == BCTS_CORR_EXACT_GEV) gev_coeffs(ri.A, ri.d, &pe, &po);
+      else eq6_coeffs(ri.A, ri.d, &pe, &po);
+      ri.pen_e = (float)pe;
+      ri.pen_o = (float)po;
+    }
+  }
+  // eval segments: per root, leaves, depth-1 nodes, root
+  long long item = 0;
+  for (int r = 0; r < n; ++r) {
+    RootInfo& ri = p.roots[r];
+    ri.leaf_item = ri.d1_item = ri.root_item = -1;
+    if (ri.d >= 1) {
+      long long cnt = 1;
+      for (int k = 0; k < ri.d; ++k) cnt *= ri.A;
+      p.segs.push_back(Seg{item, r, ri.d, ri.A, 0});
+      ri.leaf_item = item;
+      item += cnt;
+    }
+    if (ri.corr && ri.d >= 2) {
+      p.segs.push_back(Seg{item, r, 1, ri.A, 1});
+      ri.d1_item = item;
+      item += ri.A;
+    }
+    if (ri.d == 0 || ri.corr) {
+      p.segs.push_back(Seg{item, r, 0, ri.A, 2});
+      ri.root_item = item;
+      item += 1;
+    }
+  }
+  p.n_items = item;
+  p.chunk = std::min(item, chunk_items);
+  if (p.chunk < 1) p.chunk = 1;
+
+  // arena layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
+  p.o_roots = take(sizeof(RootInfo) * n);
+  p.o_segs = take(sizeof(Seg) * p.segs.size());
+  for (int k = 1; k <= p.maxd; ++k) {
+    p.o_lroot[k] = take(sizeof(int) * p.lvl_root[k].size());
+    p.o_lstart[k] = take(sizeof(long long) * p.lvl_start[k].size());
+  }
+  p.table_bytes = o;
+  if (host_io) {
+    p.o_root_pos = take(sizeof(int32_t) * n * kSprites * 2);
+    p.o_root_stack = take((size_t)n * 4 * kFrameBytes);
+    p.o_act = take(sizeof(int32_t) * n);
+    p.o_q = take(sizeof(float) * (size_t)n * q_stride);
+  }
+  for (int k = 1; k <= p.maxd; ++k) {
+    p.o_pos[k] = take((size_t)p.lvl_count[k] * 16);
+    p.o_frames[k] = take((size_t)p.lvl_count[k] * kFrameBytes);
+    p.o_ret[k] = take((size_t)p.lvl_count[k] * sizeof(float));
+    p.o_rew[k] = take((size_t)p.lvl_count[k]);
+  }
+  p.o_V = take(sizeof(float) * p.n_items);
+  p.o_q0 = take(sizeof(float) * (size_t)n * kMaxA);
+  p.o_desc = take(sizeof(ItemDesc) * p.chunk);
+  p.o_ws = take(qnet_workspace_bytes(p.chunk, prec));
+  p.total = o;
+}
+
+// Copy the plan's tables to `arena` through the pinned staging buffer `h`
+// (at least p.table_bytes; the caller makes sure no earlier copy still reads it).
+bcts_status upload_tables_at(bcts_ctx* c, const Plan& p, char* arena, char* h, hipStream_t s) {
+  std::memcpy(h + p.o_roots, p.roots.data(), sizeof(RootInfo) * p.n);
+  std::memcpy(h + p.o_segs, p.segs.data(), sizeof(Seg) * p.segs.size());
+  for (int k = 1; k <= p.maxd; ++k) {
+    std::memcpy(h + p.o_lroot[k], p.lvl_root[k].data(), sizeof(int) * p.lvl_root[k].size());
+    std::memcpy(h + p.o_lstart[k], p.lvl_start[k].data(), sizeof(long long) * p.lvl_start[k].size());
+  }
+  HIPCHECK(c, hipMemcpyAsync(arena, h, p.table_bytes, hipMemcpyHostToDevice, s));
+  return BCTS_OK;
+}
+
+bcts_status upload_tables(bcts_ctx* c, const Plan& p, hipStream_t s) {
+  bcts_status st = ensure_pinned(c, p.table_bytes);
+  if (st != BCTS_OK) return st;
+  HIPCHECK(c, hipStreamSynchronize(s));     // staging may still feed an earlier copy
+  return upload_tables_at(c, p, c->arena, c->pinned, s);
+}
+
+// Enqueue the kernels of a planned search.  Root inputs and outputs are
+// device pointers.
+bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t* d_pos,
+                              const uint8_t* d_stacks, float gamma, float corr_scale, int32_t* d_act,
+                              float* d_q, hipStream_t s, bool timed) {
+  const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
+  if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
+  double g = 1.0;
+  for (int k = 1; k <= p.maxd; ++k) {
+    LevelRoots lr{reinterpret_cast<const int*>(A + p.o_lroot[k]),
+                  reinterpret_cast<const long long*>(A + p.o_lstart[k]), (int)p.lvl_root[k].size()};
+    launch_expand(k, p.lvl_count[k], lr, roots, d_pos,
+                  k > 1 ? reinterpret_cast<const uint8_t*>(A + p.o_pos[k - 1]) : nullptr,
+                  k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr, c->env, (float)g,
+                  reinterpret_cast<uint8_t*>(A + p.o_pos[k]), reinterpret_cast<uint8_t*>(A + p.o_frames[k]),
+                  reinterpret_cast<float*>(A + p.o_ret[k]), reinterpret_cast<uint8_t*>(A + p.o_rew[k]), s);
+    g *= gamma;
+  }
+  if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
+  FrameBases fb{};
+  fb.level_frames[0] = d_stacks;
+  for (int k = 1; k <= p.maxd; ++k) fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
+  ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
+  float* V = reinterpret_cast<float*>(A + p.o_V);
+  float* q0 = reinterpret_cast<float*>(A + p.o_q0);
+  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk) {
+    const long long cnt = std::min(p.chunk, p.n_items - i0);
+    launch_item_desc(i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
+    launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + i0, q0, s);
+  }
+  if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+  LevelRet lr{};
+  for (int k = 1; k <= p.maxd; ++k) lr.ret[k] = reinterpret_cast<const float*>(A + p.o_ret[k]);
+  launch_backup_correct(p.n, roots, V, q0, lr, gamma, corr_scale, d_act, d_q, s);
+  if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
+  HIPCHECK(c, hipGetLastError());
+  return BCTS_OK;
+}
+
+bcts_status enqueue_search(bcts_ctx* c, const Plan& p, const int32_t* d_pos, const uint8_t* d_stacks,
+                           float gamma, float corr_scale, int32_t* d_act, float* d_q, hipStream_t s,
+                           bool timed) {
+  return enqueue_search_at(c, p, c->arena, d_pos, d_stacks, gamma, corr_scale, d_act, d_q, s, timed);
+}
+
+bcts_status collect_timing(bcts_ctx* c) {
+  HIPCHECK(c, hipEventSynchronize(c->ev[3]));
+  float a, b, d, e;
+  HIPCHECK(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+  HIPCHECK(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+  HIPCHECK(c, hipEventElapsedTime(&d, c->ev[2], c->ev[3]));
+  HIPCHECK(c, hipEventElapsedTime(&e, c->ev[0], c->ev[3]));
+  c->t_ms[0] = a; c->t_ms[1] = b; c->t_ms[2] = d; c->t_ms[3] = e;
+  return BCTS_OK;
+}
+
+// Host-buffer search: stage inputs, run, copy results back.
+bcts_status search_host(bcts_ctx* c, int n, const int32_t* pos, const uint8_t* stacks, const int32_t* depth,
+                        const int32_t* Av, float gamma, const bcts_correction& corr, int32_t* out_action,
+                        float* out_q, int q_stride) {
+  Plan p;
+  make_plan(p, n, depth, Av, gamma, corr, q_stride, c->chunk_items, c->prec, true);
+  bcts_status st = ensure_arena(c, p.total);
+  if (st != BCTS_OK) return st;
+  hipStream_t s = c->stream;
+  st = upload_tables(c, p, s);
+  if (st != BCTS_OK) return st;
+  const size_t in_bytes = sizeof(int32_t) * n * kSprites * 2 + (size_t)n * 4 * kFrameBytes;
+  const size_t out_bytes = sizeof(int32_t) * n + sizeof(float) * (size_t)n * q_stride;
+  st = ensure_pinned(c, std::max(p.table_bytes, std::max(in_bytes, out_bytes)));
+  if (st != BCTS_OK) return st;
+  HIPCHECK(c, hipStreamSynchronize(s));
+  std::memcpy(c->pinned, pos, sizeof(int32_t) * n * kSprites * 2);
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_pos, c->pinned, sizeof(int32_t) * n * kSprites * 2,
+                             hipMemcpyHostToDevice, s));
+  // stacks can be large: copy directly (synchronous for pageable memory)
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_stack, stacks, (size_t)n * 4 * kFrameBytes,
+                             hipMemcpyHostToDevice, s));
+  int32_t* d_act = reinterpret_cast<int32_t*>(c->arena + p.o_act);
+  float* d_q = reinterpret_cast<float*>(c->arena + p.o_q);
+  st = enqueue_search(c, p, reinterpret_cast<const int32_t*>(c->arena + p.o_root_pos),
+                      reinterpret_cast<const uint8_t*>(c->arena + p.o_root_stack), gamma,
+                      corr.enabled ? corr.scale : 0.f, d_act, d_q, s, c->timing);
+  if (st != BCTS_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(out_action, d_act, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHECK(c, hipMemcpyAsync(out_q, d_q, sizeof(float) * (size_t)n * q_stride, hipMemcpyDeviceToHost, s));
+  HIPCHECK(c, hipStreamSynchronize(s));
+  if (c->timing) return collect_timing(c);
+  return BCTS_OK;
+}
+
+}  // namespace
+
+
+// ===========================================================================
+// Serving: continuous batching with HBM-budget admission.
+//
+// Requests are queued on submit (inputs copied).  Up to `max_inflight`
+// batches run at once, each on its own stream with its own device arena and
+// pinned staging; a batch is the longest FIFO prefix of the queue that shares
+// (gamma, correction), fits the slot's memory and has at most `max_batch`
+// requests.  Whenever a batch completes its slot is refilled, so requests that
+// arrive while others are on the GPU join the next free slot and run
+// concurrently with the batches still in flight.
+// ===========================================================================
+size_t request_bytes(int d, int A) {
+  size_t b = 0, cnt = 1;
+  for (int k = 1; k <= d; ++k) {
+    cnt *= (size_t)A;
+    b += cnt * (size_t)(kFrameBytes + 16 + 4 + 1) + 4 * kAlign;
+  }
+  const size_t items = (d >= 1 ? cnt : 0) + (d >= 2 ? (size_t)A : 0) + 1;
+  b += items * 4 + (size_t)4 * kFrameBytes + 64 + kMaxA * 4 * 2 + 4 + sizeof(RootInfo) + 3 * sizeof(Seg) +
+       kMaxD * 12 + 16 * kAlign;
+  return b;
+}
+
+struct ServeReq {
+  uint64_t ticket;
+  int A, d;
+  float gamma;
+  bcts_correction corr;
+  int32_t pos[kSprites * 2];
+  std::vector<uint8_t> stack;
+  size_t bytes;
+};
+
+struct ServeResult {
+  int action;
+  int A;
+  float q[kMaxA];
+  double t_done;
+};
+
+struct ServeSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  bool busy = false;
+  std::vector<uint64_t> tickets;
+  std::vector<int> A;
+  size_t h_act = 0, h_q = 0;   // output offsets in pinned
+};
+
+struct ServeEngine {
+  bcts_ctx* c;
+  int max_batch = 512, max_inflight = 2;
+  long long chunk = 2048;
+  size_t slot_cap = 0;
+  std::deque<ServeReq> queue;
+  std::vector<ServeSlot> slots;
+  std::unordered_map<uint64_t, ServeResult> results;
+  std::unordered_set<uint64_t> live;
+  uint64_t next_ticket = 1;
+
+  explicit ServeEngine(bcts_ctx* ctx) : c(ctx) {}
+  ~ServeEngine() { release(); }
+
+  size_t fixed_bytes() const {
+    return qnet_workspace_bytes(chunk, c->prec) + sizeof(ItemDesc) * chunk + 8 * kAlign;
+  }
+
+  void release() {
+    for (auto& sl : slots) {
+      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+      if (sl.arena) (void)hipFree(sl.arena);
+      if (sl.pinned) (void)hipHostFree(sl.pinned);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    slots.clear();
+  }
+
+  void drop_all() {
+    release();
+    queue.clear();
+    results.clear();
+    live.clear();
+  }
+
+  bcts_status init() {
+    if (!slots.empty()) return BCTS_OK;
+    const size_t used = c->wbytes + c->arena_bytes;
+    const size_t avail = c->budget > used ? c->budget - used : 0;
+    slot_cap = avail / (size_t)max_inflight;
+    if (slot_cap <= fixed_bytes())
+      return fail(c, BCTS_E_NOMEM, "serving budget too small (%zu bytes per slot)", slot_cap);
+    slots.resize(max_inflight);
+    for (auto& sl : slots) {
+      HIPCHECK(c, hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+      HIPCHECK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    }
+    return BCTS_OK;
+  }
+
+  bcts_status retire() {
+    for (auto& sl : slots) {
+      if (!sl.busy) continue;
+      hipError_t e = hipEventQuery(sl.done);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return fail(c, BCTS_E_HIP, "serving batch failed: %s", hipGetErrorString(e));
+      const double t = now_s();
+      const int32_t* act = reinterpret_cast<const int32_t*>(sl.pinned + sl.h_act);
+      const float* q = reinterpret_cast<const float*>(sl.pinned + sl.h_q);
+      for (size_t i = 0; i < sl.tickets.size(); ++i) {
+        ServeResult r;
+        r.action = act[i];
+        r.A = sl.A[i];
+        for (int a = 0; a < kMaxA; ++a) r.q[a] = q[i * kMaxA + a];
+        r.t_done = t;
+        if (live.count(sl.tickets[i])) results[sl.tickets[i]] = r;
+      }
+      sl.busy = false;
+    }
+    return BCTS_OK;
+  }
+
+  bcts_status launch(ServeSlot& sl) {
+    // FIFO prefix sharing (gamma, correction) within the slot's memory
+    const size_t cap = slot_cap - fixed_bytes();
+    const ServeReq& f = queue.front();
+    size_t sum = 0;
+    int n = 0;
+    for (const auto& r : queue) {
+      if (n >= max_batch || r.gamma != f.gamma || r.corr.enabled != f.corr.enabled ||
+          r.corr.scale != f.corr.scale || r.corr.mode != f.corr.mode || sum + r.bytes > cap)
+        break;
+      sum += r.bytes;
+      ++n;
+    }
+    if (n == 0) return BCTS_OK;
+    std::vector<int32_t> dep(n), Av(n);
+    for (int i = 0; i < n; ++i) { dep[i] = queue[i].d; Av[i] = queue[i].A; }
+    Plan p;
+    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk, c->prec, true);
+    while (p.total > slot_cap && n > 1) {   // alignment slack: shrink the batch
+      --n;
+      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk, c->prec, true);
+    }
+    if (p.total > slot_cap) return fail(c, BCTS_E_NOMEM, "request does not fit a serving slot");
+    if (sl.arena_bytes < slot_cap) {
+      if (sl.arena) HIPCHECK(c, hipFree(sl.arena));
+      sl.arena = nullptr;
+      sl.arena_bytes = 0;
+      HIPCHECK(c, hipMalloc((void**)&sl.arena, slot_cap));
+      sl.arena_bytes = slot_cap;
+    }
+    const size_t in_pos = align_up(p.table_bytes), in_stack = in_pos + align_up(sizeof(int32_t) * n * 16);
+    sl.h_act = in_stack + align_up((size_t)n * 4 * kFrameBytes);
+    sl.h_q = sl.h_act + align_up(sizeof(int32_t) * n);
+    const size_t need = sl.h_q + align_up(sizeof(float) * (size_t)n * kMaxA);
+    if (sl.pinned_bytes < need) {
+      if (sl.pinned) HIPCHECK(c, hipHostFree(sl.pinned));
+      sl.pinned = nullptr;
+      sl.pinned_bytes = 0;
+      const size_t nb = std::max(need * 2, (size_t)1 << 20);
+      HIPCHECK(c, hipHostMalloc((void**)&sl.pinned, nb, hipHostMallocDefault));
+      sl.pinned_bytes = nb;
+    }
+    bcts_status st = upload_tables_at(c, p, sl.arena, sl.pinned, sl.stream);
+    if (st != BCTS_OK) return st;
+    int32_t* hp = reinterpret_cast<int32_t*>(sl.pinned + in_pos);
+    uint8_t* hs = reinterpret_cast<uint8_t*>(sl.pinned + in_stack);
+    sl.tickets.resize(n);
+    sl.A.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const ServeReq& r = queue[i];
+      std::memcpy(hp + i * 16, r.pos, sizeof r.pos);
+      std::memcpy(hs + (size_t)i * 4 * kFrameBytes, r.stack.data(), (size_t)4 * kFrameBytes);
+      sl.tickets[i] = r.ticket;
+      sl.A[i] = r.A;
+    }
+    HIPCHECK(c, hipMemcpyAsync(sl.arena + p.o_root_pos, hp, sizeof(int32_t) * n * 16, hipMemcpyHostToDevice,
+                               sl.stream));
+    HIPCHECK(c, hipMemcpyAsync(sl.arena + p.o_root_stack, hs, (size_t)n * 4 * kFrameBytes,
+                               hipMemcpyHostToDevice, sl.stream));
+    int32_t* d_act = reinterpret_cast<int32_t*>(sl.arena + p.o_act);
+    float* d_q = reinterpret_cast<float*>(sl.arena + p.o_q);
+    st = enqueue_search_at(c, p, sl.arena, reinterpret_cast<const int32_t*>(sl.arena + p.o_root_pos),
+                           reinterpret_cast<const uint8_t*>(sl.arena + p.o_root_stack), f.gamma,
+                           f.corr.enabled ? f.corr.scale : 0.f, d_act, d_q, sl.stream, false);
+    if (st != BCTS_OK) return st;
+    HIPCHECK(c, hipMemcpyAsync(sl.pinned + sl.h_act, d_act, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                               sl.stream));
+    HIPCHECK(c, hipMemcpyAsync(sl.pinned + sl.h_q, d_q, sizeof(float) * (size_t)n * kMaxA,
+                               hipMemcpyDeviceToHost, sl.stream));
+    HIPCHECK(c, hipEventRecord(sl.done, sl.stream));
+    sl.busy = true;
+    for (int i = 0; i < n; ++i) queue.pop_front();
+    return BCTS_OK;
+  }
+
+  bcts_status progress(int* pending) {
+    bcts_status st = init();
+    if (st != BCTS_OK) return st;
+    if ((st = retire()) != BCTS_OK) return st;
+    for (auto& sl : slots) {
+      if (queue.empty()) break;
+      if (sl.busy) continue;
+      if ((st = launch(sl)) != BCTS_OK) return st;
+    }
+    if (pending) {
+      int busy = 0;
+      for (auto& sl : slots) busy += sl.busy ? (int)sl.tickets.size() : 0;
+      *pending = (int)queue.size() + busy;
+    }
+    return BCTS_OK;
+  }
+};
+
+// ===========================================================================
+extern "C" {
+
+bcts_status bcts_create(int hip_device, size_t hbm_budget_bytes, bcts_ctx** out) {
+  if (!out) return BCTS_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    (void)hipGetLastError();
+    return BCTS_E_HIP;
+  }
+  if (hipSetDevice(hip_device) != hipSuccess) return BCTS_E_HIP;
+  bcts_ctx* c = new bcts_ctx();
+  c->device = hip_device;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete c; return BCTS_E_HIP; }
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return BCTS_E_HIP; }
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return BCTS_E_HIP; }
+  *out = c;
+  return BCTS_OK;
+}
+
+void bcts_destroy(bcts_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c->serve;
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->wmem) (void)hipFree(c->wmem);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* bcts_last_error(const bcts_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+bcts_status bcts_reset(bcts_ctx* c) {
+  if (!c) return BCTS_E_INVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipGetLastError();
+  if (c->serve) c->serve->drop_all();
+  if (c->arena) (void)hipFree(c->arena);
+  c->arena = nullptr;
+  c->arena_bytes = 0;
+  c->error_state = false;
+  c->err.clear();
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_env(bcts_ctx* c, const bcts_env_params* env) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (!env) return fail(c, BCTS_E_INVAL, "env is NULL");
+  for (int a = 0; a < kMaxA; ++a)
+    for (int k = 0; k < 2; ++k)
+      if (env->delta[a][k] < -3 || env->delta[a][k] > 3)
+        return fail(c, BCTS_E_INVAL, "delta[%d] outside [-3,3]", a);
+  for (int i = 0; i < kSprites - 1; ++i)
+    for (int k = 0; k < 2; ++k)
+      if (env->vel[i][k] < -2 || env->vel[i][k] > 2)
+        return fail(c, BCTS_E_INVAL, "vel[%d] outside [-2,2]", i);
+  std::memcpy(c->env.delta, env->delta, sizeof c->env.delta);
+  std::memcpy(c->env.vel, env->vel, sizeof c->env.vel);
+  c->env_set = true;
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (!blob) return fail(c, BCTS_E_INVAL, "blob is NULL");
+  if (n_floats != (size_t)BCTS_QNET_NUMEL)
+    return fail(c, BCTS_E_INVAL, "blob has %zu floats, expected %d", n_floats, BCTS_QNET_NUMEL);
+  for (size_t i = 0; i < n_floats; ++i)
+    if (!std::isfinite(blob[i])) return fail(c, BCTS_E_INVAL, "blob[%zu] is not finite", i);
+  HIPCHECK(c, hipSetDevice(c->device));
+  // re-layout to W[N][K] with the K orders of the implicit GEMMs
+  static const int NK[5][2] = {{32, 256}, {64, 512}, {64, 576}, {512, 3136}, {32, 512}};
+  std::vector<float> W[5], B[5];
+  const float* p = blob;
+  const float* c1w = p; p += 32 * 256;  const float* c1b = p; p += 32;
+  const float* c2w = p; p += 64 * 512;  const float* c2b = p; p += 64;
+  const float* c3w = p; p += 64 * 576;  const float* c3b = p; p += 64;
+  const float* f1w = p; p += 512 * 3136; const float* f1b = p; p += 512;
+  const float* f2w = p; p += 18 * 512;  const float* f2b = p; p += 18;
+  for (int l = 0; l < 5; ++l) { W[l].assign((size_t)NK[l][0] * NK[l][1], 0.f); B[l].assign(NK[l][0], 0.f); }
+  std::memcpy(W[0].data(), c1w, sizeof(float) * 32 * 256);            // (c, kh, kw) as OIHW
+  for (int o = 0; o < 64; ++o)
+    for (int ci = 0; ci < 32; ++ci)
+      for (int kh = 0; kh < 4; ++kh)
+        for (int kw = 0; kw < 4; ++kw)
+          W[1][(size_t)o * 512 + (kh * 4 + kw) * 32 + ci] = c2w[((o * 32 + ci) * 4 + kh) * 4 + kw];
+  for (int o = 0; o < 64; ++o)
+    for (int ci = 0; ci < 64; ++ci)
+      for (int kh = 0; kh < 3; ++kh)
+        for (int kw = 0; kw < 3; ++kw)
+          W[2][(size_t)o * 576 + (kh * 3 + kw) * 64 + ci] = c3w[((o * 64 + ci) * 3 + kh) * 3 + kw];
+  for (int o = 0; o < 512; ++o)
+    for (int ci = 0; ci < 64; ++ci)
+      for (int hw = 0; hw < 49; ++hw)
+        W[3][(size_t)o * 3136 + hw * 64 + ci] = f1w[(size_t)o * 3136 + ci * 49 + hw];
+  std::memcpy(W[4].data(), f2w, sizeof(float) * 18 * 512);              // rows 18..31 stay 0
+  std::memcpy(B[0].data(), c1b, sizeof(float) * 32);
+  std::memcpy(B[1].data(), c2b, sizeof(float) * 64);
+  std::memcpy(B[2].data(), c3b, sizeof(float) * 64);
+  std::memcpy(B[3].data(), f1b, sizeof(float) * 512);
+  std::memcpy(B[4].data(), f2b, sizeof(float) * 18);
+
+  size_t off[5][4], o = 0;   // fp32 w, bf16 w, fp8 w, bias
+  for (int l = 0; l < 5; ++l) {
+    const size_t n = W[l].size();
+    off[l][0] = o; o += align_up(n * 4);
+    off[l][1] = o; o += align_up(n * 2);
+    off[l][2] = o; o += align_up(n);
+    off[l][3] = o; o += align_up(B[l].size() * 4);
+  }
+  if (c->wmem) {
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipFree(c->wmem));
+    c->wmem = nullptr;
+  }
+  HIPCHECK(c, hipMalloc(&c->wmem, o));
+  c->wbytes = o;
+  char* base = static_cast<char*>(c->wmem);
+  for (int l = 0; l < 5; ++l) {
+    HIPCHECK(c, hipMemcpy(base + off[l][0], W[l].data(), W[l].size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(base + off[l][3], B[l].data(), B[l].size() * 4, hipMemcpyHostToDevice));
+    c->q.w[l] = reinterpret_cast<const float*>(base + off[l][0]);
+    c->q.wb[l] = reinterpret_cast<const uint16_t*>(base + off[l][1]);
+    c->q.w8[l] = reinterpret_cast<const uint8_t*>(base + off[l][2]);
+    c->q.b[l] = reinterpret_cast<const float*>(base + off[l][3]);
+    float m = 0.f;
+    for (float v : W[l]) m = std::max(m, std::fabs(v));
+    c->wabs[l] = m;
+    c->q.wscale[l] = m > 0.f ? 448.f / m : 1.f;
+    launch_convert_bf16(c->q.w[l], const_cast<uint16_t*>(c->q.wb[l]), (long long)W[l].size(), c->stream);
+    launch_convert_fp8(c->q.w[l], const_cast<uint8_t*>(c->q.w8[l]), (long long)W[l].size(), c->q.wscale[l],
+                       c->stream);
+  }
+  // activation scales until calibrated: pixels 1:1 (255 -> 256 in e4m3), others unit
+  c->q.ascale[0] = 1.f;
+  for (int l = 1; l < 5; ++l) c->q.ascale[l] = 1.f;
+  c->fp8_calibrated = false;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->qnet_set = true;
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_precision(bcts_ctx* c, bcts_precision prec) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (prec != BCTS_FP32 && prec != BCTS_BF16 && prec != BCTS_FP8)
+    return fail(c, BCTS_E_INVAL, "unknown precision %d", (int)prec);
+  c->prec = (int)prec;
+  return BCTS_OK;
+}
+
+bcts_status bcts_get_fp8_scales(bcts_ctx* c, float* out5) {
+  if (!c || !out5) return BCTS_E_INVAL;
+  for (int l = 0; l < 5; ++l) out5[l] = c->q.ascale[l];
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_fp8_scales(bcts_ctx* c, const float* in5) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (!in5) return fail(c, BCTS_E_INVAL, "scales are NULL");
+  for (int l = 0; l < 5; ++l)
+    if (!(in5[l] > 0.f) || !std::isfinite(in5[l])) return fail(c, BCTS_E_INVAL, "scale %d not positive", l);
+  for (int l = 0; l < 5; ++l) c->q.ascale[l] = in5[l];
+  c->fp8_calibrated = true;
+  return BCTS_OK;
+}
+
+bcts_status bcts_calibrate_fp8(bcts_ctx* c, int32_t n, const uint8_t* stacks) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (n <= 0 || !stacks) return fail(c, BCTS_E_INVAL, "need n > 0 calibration stacks");
+  if (!c->qnet_set) return fail(c, BCTS_E_STATE, "no Q-network set");
+  HIPCHECK(c, hipSetDevice(c->device));
+  std::vector<int32_t> dep(n, 0), Av(n, kMaxA);
+  bcts_correction off{0, 0.f, 0};
+  Plan p;
+  make_plan(p, n, dep.data(), Av.data(), 1.f, off, kMaxA, n, P_FP32, true);
+  const size_t maxb = p.total + 64;
+  st = ensure_arena(c, maxb);
+  if (st != BCTS_OK) return st;
+  hipStream_t s = c->stream;
+  st = upload_tables(c, p, s);
+  if (st != BCTS_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_stack, stacks, (size_t)n * 4 * kFrameBytes,
+                             hipMemcpyHostToDevice, s));
+  FrameBases fb{};
+  fb.level_frames[0] = reinterpret_cast<const uint8_t*>(c->arena + p.o_root_stack);
+  ItemDesc* desc = reinterpret_cast<ItemDesc*>(c->arena + p.o_desc);
+  launch_item_desc(0, n, reinterpret_cast<const Seg*>(c->arena + p.o_segs), (int)p.segs.size(),
+                   reinterpret_cast<const RootInfo*>(c->arena + p.o_roots), fb, desc, s);
+  float* ws = reinterpret_cast<float*>(c->arena + p.o_ws);
+  launch_qnet(P_FP32, c->q, desc, n, ws, reinterpret_cast<float*>(c->arena + p.o_V),
+              reinterpret_cast<float*>(c->arena + p.o_q0), s);
+  // absmax of each layer's FP32 input: x1, x2, x3, h
+  float* mx = reinterpret_cast<float*>(c->arena + p.total);
+  HIPCHECK(c, hipMemsetAsync(mx, 0, 16, s));
+  const long long sz[4] = {12800LL * n, 5184LL * n, 3136LL * n, 512LL * n};
+  const float* src = ws;
+  for (int l = 0; l < 4; ++l) {
+    launch_absmax(src, sz[l], mx + l, s);
+    src += sz[l];
+  }
+  float h[4];
+  HIPCHECK(c, hipMemcpyAsync(h, mx, 16, hipMemcpyDeviceToHost, s));
+  HIPCHECK(c, hipStreamSynchronize(s));
+  c->q.ascale[0] = 1.f;
+  for (int l = 0; l < 4; ++l) c->q.ascale[l + 1] = h[l] > 0.f ? 448.f / h[l] : 1.f;
+  c->fp8_calibrated = true;
+  return BCTS_OK;
+}
+
+bcts_status bcts_search(bcts_ctx* c, int32_t n, const int32_t* pos, const uint8_t* stacks, int32_t depth,
+                        int32_t A, float gamma, bcts_correction corr, int32_t* out_action, float* out_q) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
+  if ((st = validate_shape(c, A, depth, corr)) != BCTS_OK) return st;
+  if (!pos || !stacks || !out_action || !out_q) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  if ((st = validate_pos(c, n, pos)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  std::vector<int32_t> dv(n, depth), av(n, A);
+  return search_host(c, n, pos, stacks, dv.data(), av.data(), gamma, corr, out_action, out_q, A);
+}
+
+bcts_status bcts_search_batch(bcts_ctx* c, int32_t n, const int32_t* pos, const uint8_t* stacks,
+                              const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                              int32_t* out_action, float* out_q) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
+  if (!pos || !stacks || !out_action || !out_q || !depth || !A) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  for (int r = 0; r < n; ++r)
+    if ((st = validate_shape(c, A[r], depth[r], corr)) != BCTS_OK) return st;
+  if ((st = validate_pos(c, n, pos)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  return search_host(c, n, pos, stacks, depth, A, gamma, corr, out_action, out_q, kMaxA);
+}
+
+bcts_status bcts_search_batch_device(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
+                                     const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                                     int32_t* d_act, float* d_q, void* hip_stream) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
+  if (!d_pos || !d_stacks || !d_act || !d_q || !depth || !A) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  for (int r = 0; r < n; ++r)
+    if ((st = validate_shape(c, A[r], depth[r], corr)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  Plan p;
+  make_plan(p, n, depth, A, gamma, corr, kMaxA, c->chunk_items, c->prec, false);
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
+  st = enqueue_search(c, p, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, s, c->timing);
+  if (st != BCTS_OK) return st;
+  if (c->timing) return collect_timing(c);
+  return BCTS_OK;
+}
+
+bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
+                                    const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                                    int32_t* d_act, float* d_q, int32_t replays, void* hip_stream) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
+  if (!d_pos || !d_stacks || !d_act || !d_q || !depth || !A) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  if (replays < 1) return fail(c, BCTS_E_INVAL, "replays must be >= 1");
+  for (int r = 0; r < n; ++r)
+    if ((st = validate_shape(c, A[r], depth[r], corr)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  Plan p;
+  make_plan(p, n, depth, A, gamma, corr, kMaxA, c->chunk_items, c->prec, false);
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
+  HIPCHECK(c, hipStreamSynchronize(s));
+  hipStream_t cap;
+  HIPCHECK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = enqueue_search(c, p, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, cap, false);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (st == BCTS_OK && e2 != hipSuccess) e = e2;
+  }
+  if (e == hipSuccess && st == BCTS_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess && st == BCTS_OK) {
+    if (c->timing) e = hipEventRecord(c->ev[0], s);
+    for (int i = 0; i < replays && e == hipSuccess; ++i) e = hipGraphLaunch(exec, s);
+    if (c->timing && e == hipSuccess) e = hipEventRecord(c->ev[3], s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (st != BCTS_OK) return st;
+  if (e != hipSuccess) return fail(c, BCTS_E_HIP, "graph capture/replay failed: %s", hipGetErrorString(e));
+  if (c->timing) {
+    float ms = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+    c->t_ms[0] = c->t_ms[1] = c->t_ms[2] = 0.0;
+    c->t_ms[3] = ms / replays;
+  }
+  return BCTS_OK;
+}
+
+bcts_status bcts_debug_expand(bcts_ctx* c, const int32_t* pos, const uint8_t* stack, int32_t depth, int32_t A,
+                              int32_t* out_pos, uint8_t* out_frames, int32_t* out_reward) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  bcts_correction off{0, 0.f, 0};
+  if ((st = validate_common(c, 1, 0.5f, off)) != BCTS_OK) return st;
+  if ((st = validate_shape(c, A, depth, off)) != BCTS_OK) return st;
+  if (depth < 1) return fail(c, BCTS_E_INVAL, "debug expansion needs depth >= 1");
+  if (!pos || !stack || !out_pos || !out_frames || !out_reward) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  if ((st = validate_pos(c, 1, pos)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan p;
+  make_plan(p, 1, &depth, &A, 1.f, off, A, c->chunk_items, c->prec, true);
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  hipStream_t s = c->stream;
+  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_pos, pos, sizeof(int32_t) * 16, hipMemcpyHostToDevice, s));
+  char* Ar = c->arena;
+  const RootInfo* roots = reinterpret_cast<const RootInfo*>(Ar + p.o_roots);
+  for (int k = 1; k <= depth; ++k) {
+    LevelRoots lr{reinterpret_cast<const int*>(Ar + p.o_lroot[k]),
+                  reinterpret_cast<const long long*>(Ar + p.o_lstart[k]), (int)p.lvl_root[k].size()};
+    launch_expand(k, p.lvl_count[k], lr, roots, reinterpret_cast<const int32_t*>(Ar + p.o_root_pos),
+                  k > 1 ? reinterpret_cast<const uint8_t*>(Ar + p.o_pos[k - 1]) : nullptr,
+                  k > 1 ? reinterpret_cast<const float*>(Ar + p.o_ret[k - 1]) : nullptr, c->env, 1.f,
+                  reinterpret_cast<uint8_t*>(Ar + p.o_pos[k]), reinterpret_cast<uint8_t*>(Ar + p.o_frames[k]),
+                  reinterpret_cast<float*>(Ar + p.o_ret[k]), reinterpret_cast<uint8_t*>(Ar + p.o_rew[k]), s);
+  }
+  HIPCHECK(c, hipGetLastError());
+  HIPCHECK(c, hipStreamSynchronize(s));
+  long long at = 0;
+  for (int k = 1; k <= depth; ++k) {
+    const long long nk = p.lvl_count[k];
+    std::vector<uint8_t> pb((size_t)nk * 16), rb((size_t)nk);
+    HIPCHECK(c, hipMemcpy(pb.data(), Ar + p.o_pos[k], pb.size(), hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(rb.data(), Ar + p.o_rew[k], rb.size(), hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(out_frames + at * kFrameBytes, Ar + p.o_frames[k], (size_t)nk * kFrameBytes,
+                          hipMemcpyDeviceToHost));
+    for (long long i = 0; i < nk; ++i) {
+      for (int q = 0; q < 16; ++q) out_pos[(at + i) * 16 + q] = pb[i * 16 + q];
+      out_reward[at + i] = rb[i];
+    }
+    at += nk;
+  }
+  (void)stack;
+  return BCTS_OK;
+}
+
+bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32_t A, float* out_q) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (n <= 0 || !stacks || !out_q) return fail(c, BCTS_E_INVAL, "bad arguments");
+  if (A < 1 || A > kMaxA) return fail(c, BCTS_E_INVAL, "A=%d outside [1,18]", A);
+  if (!c->qnet_set) return fail(c, BCTS_E_STATE, "no Q-network set");
+  HIPCHECK(c, hipSetDevice(c->device));
+  std::vector<int32_t> dep(n, 0), Av(n, A);
+  bcts_correction off{0, 0.f, 0};
+  Plan p;
+  make_plan(p, n, dep.data(), Av.data(), 1.f, off, kMaxA, c->chunk_items, c->prec, true);
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  hipStream_t s = c->stream;
+  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_stack, stacks, (size_t)n * 4 * kFrameBytes,
+                             hipMemcpyHostToDevice, s));
+  FrameBases fb{};
+  fb.level_frames[0] = reinterpret_cast<const uint8_t*>(c->arena + p.o_root_stack);
+  ItemDesc* desc = reinterpret_cast<ItemDesc*>(c->arena + p.o_desc);
+  float* q0 = reinterpret_cast<float*>(c->arena + p.o_q0);
+  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk) {
+    const long long cnt = std::min(p.chunk, p.n_items - i0);
+    launch_item_desc(i0, cnt, reinterpret_cast<const Seg*>(c->arena + p.o_segs), (int)p.segs.size(),
+                     reinterpret_cast<const RootInfo*>(c->arena + p.o_roots), fb, desc, s);
+    launch_qnet(c->prec, c->q, desc, cnt, c->arena + p.o_ws, reinterpret_cast<float*>(c->arena + p.o_V) + i0,
+                q0, s);
+  }
+  HIPCHECK(c, hipGetLastError());
+  std::vector<float> h((size_t)n * kMaxA);
+  HIPCHECK(c, hipMemcpyAsync(h.data(), q0, h.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(c, hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < A; ++a) out_q[(size_t)i * A + a] = h[(size_t)i * kMaxA + a];
+  return BCTS_OK;
+}
+
+size_t bcts_request_bytes(int32_t depth, int32_t A) {
+  if (A < 1 || A > kMaxA || depth < 0 || depth > kMaxD) return 0;
+  return request_bytes(depth, A);
+}
+
+bcts_status bcts_serve_config(bcts_ctx* c, int32_t max_batch, int32_t max_inflight) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (max_batch < 1 || max_inflight < 1 || max_inflight > 8)
+    return fail(c, BCTS_E_INVAL, "max_batch >= 1 and 1 <= max_inflight <= 8");
+  if (c->serve && (!c->serve->queue.empty() || !c->serve->live.empty()))
+    return fail(c, BCTS_E_STATE, "serving is active");
+  delete c->serve;
+  c->serve = new ServeEngine(c);
+  c->serve->max_batch = max_batch;
+  c->serve->max_inflight = max_inflight;
+  return BCTS_OK;
+}
+
+bcts_status bcts_submit(bcts_ctx* c, const int32_t* pos, const uint8_t* stack, int32_t depth, int32_t A,
+                        float gamma, bcts_correction corr, uint64_t* ticket) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, 1, gamma, corr)) != BCTS_OK) return st;
+  if ((st = validate_shape(c, A, depth, corr)) != BCTS_OK) return st;
+  if (!pos || !stack || !ticket) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  if ((st = validate_pos(c, 1, pos)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  if (!c->serve) c->serve = new ServeEngine(c);
+  ServeEngine& e = *c->serve;
+  if ((st = e.init()) != BCTS_OK) return st;
+  ServeReq r;
+  r.bytes = request_bytes(depth, A);
+  if (r.bytes > e.slot_cap - e.fixed_bytes())
+    return fail(c, BCTS_E_NOMEM, "request (depth %d, A %d) needs %zu bytes; a serving slot holds %zu", depth, A,
+                r.bytes, e.slot_cap - e.fixed_bytes());
+  r.ticket = e.next_ticket++;
+  r.A = A;
+  r.d = depth;
+  r.gamma = gamma;
+  r.corr = corr;
+  std::memcpy(r.pos, pos, sizeof r.pos);
+  r.stack.assign(stack, stack + (size_t)4 * kFrameBytes);
+  e.live.insert(r.ticket);
+  *ticket = r.ticket;
+  e.queue.push_back(std::move(r));
+  return e.progress(nullptr);
+}
+
+bcts_status bcts_progress(bcts_ctx* c, int32_t* pending) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (!c->serve) {
+    if (pending) *pending = 0;
+    return BCTS_OK;
+  }
+  HIPCHECK(c, hipSetDevice(c->device));
+  return c->serve->progress(pending);
+}
+
+bcts_status bcts_poll(bcts_ctx* c, uint64_t ticket, int32_t* action, float* q, double* t_done) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (!c->serve || !c->serve->live.count(ticket)) return fail(c, BCTS_E_STATE, "unknown ticket %llu",
+                                                             (unsigned long long)ticket);
+  HIPCHECK(c, hipSetDevice(c->device));
+  if ((st = c->serve->progress(nullptr)) != BCTS_OK) return st;
+  auto it = c->serve->results.find(ticket);
+  if (it == c->serve->results.end()) return BCTS_E_BUSY;
+  if (action) *action = it->second.action;
+  if (q)
+    for (int a = 0; a < it->second.A; ++a) q[a] = it->second.q[a];
+  if (t_done) *t_done = it->second.t_done;
+  c->serve->results.erase(it);
+  c->serve->live.erase(ticket);
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_timing(bcts_ctx* c, int32_t enabled) {
+  if (!c) return BCTS_E_INVAL;
+  c->timing = enabled != 0;
+  return BCTS_OK;
+}
+
+bcts_status bcts_get_timing(bcts_ctx* c, double* out4) {
+  if (!c || !out4) return BCTS_E_INVAL;
+  for (int i = 0; i < 4; ++i) out4[i] = c->t_ms[i];
+  return BCTS_OK;
+}
+
+}  // extern "C"

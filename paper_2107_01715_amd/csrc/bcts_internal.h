@@ -1,0 +1,119 @@
+// Internal declarations shared by the translation units of libbcts.
+// Device data layout (all per search batch, in the context's HBM arena):
+//
+//   root_pos    int32 [n][8][2]            root positions (x, y)
+//   root_stack  uint8 [n][4][7056]         root frame stacks, channel 0 oldest
+//   level k = 1..maxd (nodes of every root with depth >= k, root-major,
+//   inside a root in the index order of Alg. 1: child a of node j is j*A + a)
+//     pos_k     uint8 [N_k][16]            (x0, y0, x1, y1, ...) after the move
+//     frame_k   uint8 [N_k][7056]          the frame rendered at that node
+//     ret_k     float [N_k]                sum_{t<k} gamma^t r_t along the path
+//     rew_k     uint8 [N_k]                the reward of the step into the node
+//   eval items (the nodes whose stack goes through the Q-network), grouped in
+//   segments of one (root, level): leaves, depth-1 nodes, roots
+//     V         float [n_items]            max_{a<A} Q(s, a)
+//     q0        float [n][18]              Q(s_0, .) of root evaluations
+//
+// A node's 4-frame stack is never materialised: channel c of a level-m node
+// is the frame of its ancestor at level m-3+c (the root's stack for levels
+// <= 0).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcts {
+
+constexpr int kFrame = 84;
+constexpr int kFrameBytes = 84 * 84;
+constexpr int kSprites = 8;
+constexpr int kMaxA = 18;
+constexpr int kMaxD = 6;
+
+// Per-root descriptor (device resident).
+struct RootInfo {
+  int A, d;
+  float gamma_d;          // gamma^d
+  float pen_e, pen_o;     // penalty B = pen_e * d_e - pen_o * d_o
+  int corr;               // correction applied (d >= 1 and enabled)
+  int q_stride;           // output row stride of out_q
+  int pad_;
+  long long base[kMaxD + 1];   // first node of this root at level k (k >= 1)
+  long long leaf_item;         // first leaf eval item (d >= 1), else -1
+  long long d1_item;           // first depth-1 eval item (d >= 2 and corr), else -1
+  long long root_item;         // root eval item, else -1
+};
+
+// A run of eval items that belong to one root and one level.
+struct Seg {
+  long long item0;
+  int root, level, A, kind;    // kind: 0 leaf, 1 depth-1, 2 root
+};
+
+// One level's participating roots, sorted by first node.
+struct LevelRoots {
+  const int* root;             // [cnt]
+  const long long* start;      // [cnt] first node index of that root at this level
+  int cnt;
+};
+
+struct EnvTables {
+  int delta[kMaxA][2];
+  int vel[kSprites - 1][2];
+};
+
+// Per-item Q-network input/outputs for one chunk of eval items.
+struct ItemDesc {
+  const uint8_t* frame[4];     // the 4 stack frames, channel 0 oldest
+  int A;                       // valid Q outputs
+  int q0_root;                 // root id whose q0 row this item fills, or -1
+};
+
+// Where frames live: level k >= 1 at level_frames[k] (node-major, 7056 B
+// each); level_frames[0] is the root stack array [n][4][7056].
+struct FrameBases {
+  const uint8_t* level_frames[kMaxD + 1];
+};
+
+// Precisions (mirrors bcts_precision).
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
+
+// Device weights in GEMM layout W[N][K] for every precision.  K orders:
+// conv1 (c, kh, kw); conv2, conv3 (kh, kw, c); fc1 (h, w, c); fc2 (k).
+struct QnetDev {
+  const float* w[5];           // fp32
+  const uint16_t* wb[5];       // bf16 bits
+  const uint8_t* w8[5];        // e4m3 bytes (weights scaled by wscale)
+  const float* b[5];           // biases, fp32
+  float wscale[5];             // fp8 weight scale: w8 = e4m3(w * wscale)
+  float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
+};
+
+// ---- launchers (each in the TU that defines its kernels) ----------------
+void launch_expand(int k, long long n_nodes, LevelRoots lr, const RootInfo* roots,
+                   const int* root_pos, const uint8_t* prev_pos, const float* prev_ret,
+                   const EnvTables& env, float gamma_pow, uint8_t* pos, uint8_t* frames,
+                   float* ret, uint8_t* rew, hipStream_t s);
+
+void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, int nsegs,
+                      const RootInfo* roots, const FrameBases& fb, ItemDesc* out,
+                      hipStream_t s);
+
+// Q-network over a chunk of items (descs already built): writes V[item] and
+// q0 rows.  `ws` is a workspace of qnet_workspace_bytes(chunk, prec) bytes.
+size_t qnet_workspace_bytes(long long chunk, int prec);
+void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
+                 void* ws, float* V, float* q0, hipStream_t s);
+
+struct LevelRet {
+  const float* ret[kMaxD + 1];   // ret_k per level (index 0 unused)
+};
+void launch_backup_correct(int n_roots, const RootInfo* roots, const float* V, const float* q0,
+                           const LevelRet& level_ret, float gamma, float corr_scale,
+                           int* out_action, float* out_q, hipStream_t s);
+
+// fp32 -> bf16 / e4m3 conversion of weight arrays on the device
+void launch_convert_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s);
+void launch_convert_fp8(const float* src, uint8_t* dst, long long n, float scale, hipStream_t s);
+void launch_absmax(const float* src, long long n, float* out, hipStream_t s);
+
+}  // namespace bcts

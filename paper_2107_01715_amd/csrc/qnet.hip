@@ -1,0 +1,517 @@
+// Nature-DQN value network over a chunk of eval items, as implicit GEMMs on
+// the CDNA4 matrix cores (the leaf-scoring step of Alg. 1).
+//
+// Every layer is C[M][N] = act(scale * A[M][K] B[K][N] + bias) with the
+// activations kept channels-last (NHWC), so that the GEMM output of one layer
+// is, row-major, the next layer's input tensor:
+//
+//   layer  rows per item      N    K = unit order (8 K values per unit)
+//   conv1  20*20 (oy, ox)     32   256 = (c, kh) x kw[8]     from 4 uint8 frames
+//   conv2   9*9               64   512 = (kh, kw, c/8) x 8   from x1 [20][20][32]
+//   conv3   7*7               64   576 = (kh, kw, c/8) x 8   from x2 [9][9][64]
+//   fc1     1                512  3136 = (h, w, c/8) x 8     from x3 [7][7][64]
+//   fc2     1                 32   512                       from h [512]; max over A
+//
+// A workgroup (4 wavefronts) computes a BM x BN tile: im2col rows are
+// gathered unit by unit (8 contiguous K values per load) into LDS, weights
+// W[N][K] likewise, then each wavefront runs 16x16 MFMAs over its 32-row
+// slice.  Operands: FP32 (v_mfma_f32_16x16x4_f32), BF16
+// (v_mfma_f32_16x16x32_bf16) or OCP e4m3 (v_mfma_f32_16x16x32_fp8_fp8), all
+// accumulating in FP32.  The 1/255 input scaling is applied to conv1's
+// accumulator; FP8 layers rescale by 1/(input scale * weight scale).
+#include "bcts_internal.h"
+
+namespace bcts {
+namespace {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+constexpr int kThreads = 256;
+constexpr int kBM = 128;       // rows per workgroup tile
+constexpr int kBKU = 4;        // K units (of 8) per LDS stage: 32 K values
+
+// ---- element types ------------------------------------------------------
+template <int P> struct PT;
+template <> struct PT<P_FP32> { typedef float T; };
+template <> struct PT<P_BF16> { typedef uint16_t T; };
+template <> struct PT<P_FP8> { typedef uint8_t T; };
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);             // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsigned)h << 16); }
+
+// float -> OCP e4m3 (saturating to +-448), round to nearest even
+__device__ __forceinline__ uint8_t f2e4m3(float f) {
+  f = fminf(fmaxf(f, -448.f), 448.f);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false);
+  return (uint8_t)(w & 0xFF);
+}
+
+// A unit: 8 consecutive K values of one GEMM row, in the operand type.
+template <int P> struct Unit;
+template <> struct Unit<P_FP32> { float4 a, b; };
+template <> struct Unit<P_BF16> { uint4 v; };
+template <> struct Unit<P_FP8> { uint2 v; };
+
+template <int P> __device__ __forceinline__ Unit<P> zero_unit();
+template <> __device__ __forceinline__ Unit<P_FP32> zero_unit<P_FP32>() {
+  Unit<P_FP32> u; u.a = make_float4(0, 0, 0, 0); u.b = u.a; return u;
+}
+template <> __device__ __forceinline__ Unit<P_BF16> zero_unit<P_BF16>() {
+  Unit<P_BF16> u; u.v = make_uint4(0, 0, 0, 0); return u;
+}
+template <> __device__ __forceinline__ Unit<P_FP8> zero_unit<P_FP8>() {
+  Unit<P_FP8> u; u.v = make_uint2(0, 0); return u;
+}
+
+// load 8 elements of the layer's own type
+template <int P> __device__ __forceinline__ Unit<P> load_unit(const typename PT<P>::T* p);
+template <> __device__ __forceinline__ Unit<P_FP32> load_unit<P_FP32>(const float* p) {
+  Unit<P_FP32> u;
+  u.a = *reinterpret_cast<const float4*>(p);
+  u.b = *reinterpret_cast<const float4*>(p + 4);
+  return u;
+}
+template <> __device__ __forceinline__ Unit<P_BF16> load_unit<P_BF16>(const uint16_t* p) {
+  Unit<P_BF16> u; u.v = *reinterpret_cast<const uint4*>(p); return u;
+}
+template <> __device__ __forceinline__ Unit<P_FP8> load_unit<P_FP8>(const uint8_t* p) {
+  Unit<P_FP8> u; u.v = *reinterpret_cast<const uint2*>(p); return u;
+}
+
+// 8 pixels (uint8, 4-byte aligned) -> operand unit; fp8 scales the pixel
+template <int P> __device__ __forceinline__ Unit<P> pix_unit(const uint8_t* p, float s8);
+template <> __device__ __forceinline__ Unit<P_FP32> pix_unit<P_FP32>(const uint8_t* p, float) {
+  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
+  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+  Unit<P_FP32> u;
+  u.a = make_float4((float)(w0 & 255u), (float)((w0 >> 8) & 255u), (float)((w0 >> 16) & 255u),
+                    (float)(w0 >> 24));
+  u.b = make_float4((float)(w1 & 255u), (float)((w1 >> 8) & 255u), (float)((w1 >> 16) & 255u),
+                    (float)(w1 >> 24));
+  return u;
+}
+__device__ __forceinline__ unsigned pack_bf2(unsigned a, unsigned b) {
+  // integers 0..255 are exact in bf16: the float's top 16 bits
+  return (__float_as_uint((float)a) >> 16) | (__float_as_uint((float)b) & 0xFFFF0000u);
+}
+template <> __device__ __forceinline__ Unit<P_BF16> pix_unit<P_BF16>(const uint8_t* p, float) {
+  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
+  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+  Unit<P_BF16> u;
+  u.v.x = pack_bf2(w0 & 255u, (w0 >> 8) & 255u);
+  u.v.y = pack_bf2((w0 >> 16) & 255u, w0 >> 24);
+  u.v.z = pack_bf2(w1 & 255u, (w1 >> 8) & 255u);
+  u.v.w = pack_bf2((w1 >> 16) & 255u, w1 >> 24);
+  return u;
+}
+template <> __device__ __forceinline__ Unit<P_FP8> pix_unit<P_FP8>(const uint8_t* p, float s8) {
+  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
+  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+  unsigned o[2];
+  const unsigned w[2] = {w0, w1};
+  for (int h = 0; h < 2; ++h) {
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(fminf((float)(w[h] & 255u) * s8, 448.f),
+                                             fminf((float)((w[h] >> 8) & 255u) * s8, 448.f), 0, false);
+    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(fminf((float)((w[h] >> 16) & 255u) * s8, 448.f),
+                                             fminf((float)(w[h] >> 24) * s8, 448.f), lo, true);
+    o[h] = (unsigned)hi;
+  }
+  Unit<P_FP8> u; u.v = make_uint2(o[0], o[1]); return u;
+}
+
+// ---- layer geometry -----------------------------------------------------
+template <int L> struct Geo;
+template <> struct Geo<0> { static constexpr int MPI = 400, N = 32, K = 256, BN = 32; };
+template <> struct Geo<1> { static constexpr int MPI = 81, N = 64, K = 512, BN = 64; };
+template <> struct Geo<2> { static constexpr int MPI = 49, N = 64, K = 576, BN = 64; };
+template <> struct Geo<3> { static constexpr int MPI = 1, N = 512, K = 3136, BN = 128; };
+template <> struct Geo<4> { static constexpr int MPI = 1, N = 32, K = 512, BN = 32; };
+
+// Per-thread view of one GEMM row: where its units come from.
+struct RowSrc {
+  const void* base;            // layer input of the row's item (frame 0 for conv1)
+  const uint8_t* fr[4];        // conv1: the 4 frames
+  int off;                     // element offset of the row's window origin
+  bool valid;
+};
+
+template <int L, int P>
+__device__ __forceinline__ RowSrc row_src(long long m, long long M, const ItemDesc* desc,
+                                          const typename PT<P>::T* in) {
+  RowSrc r;
+  r.valid = m < M;
+  if (!r.valid) m = 0;
+  const long long item = m / Geo<L>::MPI;
+  const int pix = (int)(m - item * Geo<L>::MPI);
+  if (L == 0) {
+    const ItemDesc& d = desc[item];
+    for (int c = 0; c < 4; ++c) r.fr[c] = d.frame[c];
+    const int oy = pix / 20, ox = pix % 20;
+    r.off = oy * 4 * kFrame + ox * 4;
+    r.base = nullptr;
+  } else if (L == 1) {
+    const int oy = pix / 9, ox = pix % 9;
+    r.base = in + item * 12800;
+    r.off = (oy * 2 * 20 + ox * 2) * 32;
+  } else if (L == 2) {
+    const int oy = pix / 7, ox = pix % 7;
+    r.base = in + item * 5184;
+    r.off = (oy * 9 + ox) * 64;
+  } else if (L == 3) {
+    r.base = in + item * 3136;
+    r.off = 0;
+  } else {
+    r.base = in + item * 512;
+    r.off = 0;
+  }
+  return r;
+}
+
+template <int L, int P>
+__device__ __forceinline__ Unit<P> gather(const RowSrc& r, int U, float s8) {
+  typedef typename PT<P>::T T;
+  if (!r.valid) return zero_unit<P>();
+  if (L == 0) {
+    const int c = U >> 3, kh = U & 7;
+    return pix_unit<P>(r.fr[c] + r.off + kh * kFrame, s8);
+  } else if (L == 1) {
+    const int kh = U >> 4, kw = (U >> 2) & 3, cg = U & 3;
+    return load_unit<P>((const T*)r.base + r.off + (kh * 20 + kw) * 32 + cg * 8);
+  } else if (L == 2) {
+    const int kk = U >> 3, cg = U & 7, kh = kk / 3, kw = kk % 3;
+    return load_unit<P>((const T*)r.base + r.off + (kh * 9 + kw) * 64 + cg * 8);
+  } else {
+    return load_unit<P>((const T*)r.base + U * 8);
+  }
+}
+
+// ---- LDS tiles ----------------------------------------------------------
+// Row stride in elements: 32 K values plus padding against bank conflicts.
+template <int P> struct Lds;
+template <> struct Lds<P_FP32> { static constexpr int S = 33; };
+template <> struct Lds<P_BF16> { static constexpr int S = 40; };
+template <> struct Lds<P_FP8> { static constexpr int S = 48; };
+
+template <int P>
+__device__ __forceinline__ void st_unit(typename PT<P>::T* row, int u, const Unit<P>& v);
+template <> __device__ __forceinline__ void st_unit<P_FP32>(float* row, int u, const Unit<P_FP32>& v) {
+  float* d = row + u * 8;     // stride 33 breaks 16-byte alignment: scalar stores
+  d[0] = v.a.x; d[1] = v.a.y; d[2] = v.a.z; d[3] = v.a.w;
+  d[4] = v.b.x; d[5] = v.b.y; d[6] = v.b.z; d[7] = v.b.w;
+}
+template <> __device__ __forceinline__ void st_unit<P_BF16>(uint16_t* row, int u, const Unit<P_BF16>& v) {
+  *reinterpret_cast<uint4*>(row + u * 8) = v.v;
+}
+template <> __device__ __forceinline__ void st_unit<P_FP8>(uint8_t* row, int u, const Unit<P_FP8>& v) {
+  *reinterpret_cast<uint2*>(row + u * 8) = v.v;
+}
+
+// One 32-K stage of MFMAs for a wavefront's 32 x BN slice.
+template <int P, int NF>
+__device__ __forceinline__ void mma_stage(const typename PT<P>::T* As, const typename PT<P>::T* Bs,
+                                          int lane, f32x4 (&acc)[2][NF]) {
+  constexpr int S = Lds<P>::S;
+  const int r = lane & 15, g = lane >> 4;
+  if constexpr (P == P_FP32) {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      float a[2], b[NF];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[(i * 16 + r) * S + ks * 4 + g];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) b[j] = Bs[(j * 16 + r) * S + ks * 4 + g];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  } else if constexpr (P == P_BF16) {
+    bf16x8 a[2], b[NF];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(As + (i * 16 + r) * S + g * 8);
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(Bs + (j * 16 + r) * S + g * 8);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  } else {
+    long a[2], b[NF];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const long*>(As + (i * 16 + r) * S + g * 8);
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+      b[j] = *reinterpret_cast<const long*>(Bs + (j * 16 + r) * S + g * 8);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+template <int P> __device__ __forceinline__ void st_out(typename PT<P>::T* p, float v, float s8);
+template <> __device__ __forceinline__ void st_out<P_FP32>(float* p, float v, float) { *p = v; }
+template <> __device__ __forceinline__ void st_out<P_BF16>(uint16_t* p, float v, float) { *p = f2bf(v); }
+template <> __device__ __forceinline__ void st_out<P_FP8>(uint8_t* p, float v, float s8) { *p = f2e4m3(v * s8); }
+
+struct LayerArgs {
+  long long M;                 // rows = items * rows per item
+  const ItemDesc* desc;
+  const void* in;              // layer input (conv2..fc2)
+  const void* w;               // W[N][K] in operand type
+  const float* bias;
+  float acc_scale;             // multiplies the accumulator before the bias
+  float in_s8;                 // fp8: scale applied to the layer input (conv1 pixels)
+  float out_s8;                // fp8: scale of the next layer's input
+  void* out;                   // C (conv1..fc1)
+  float* V;                    // fc2: max_a Q per item
+  float* q0;                   // fc2: [n_roots][18]
+};
+
+template <int L, int P>
+__global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
+  typedef typename PT<P>::T T;
+  constexpr int BN = Geo<L>::BN, NF = BN / 16, K = Geo<L>::K, NU = K / 8;
+  constexpr int S = Lds<P>::S;
+  constexpr int NSTAGE = NU / kBKU;
+  static_assert(NU % kBKU == 0, "K must be a multiple of 32");
+  __shared__ __attribute__((aligned(16))) T As[kBM * S];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * S];
+  __shared__ float Cs[(L == 4) ? kBM * 33 : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long m0 = (long long)blockIdx.x * kBM;
+  const int n0 = blockIdx.y * BN;
+  const T* W = reinterpret_cast<const T*>(args.w);
+  const T* in = reinterpret_cast<const T*>(args.in);
+
+  // A: thread owns rows ra, ra + 64 and unit ua of each stage
+  const int ra = tid >> 2, ua = tid & 3;
+  RowSrc rs0 = row_src<L, P>(m0 + ra, args.M, args.desc, in);
+  RowSrc rs1 = row_src<L, P>(m0 + ra + 64, args.M, args.desc, in);
+  // B: BN rows x 4 units; thread t < BN*4 owns row t>>2 (and +64 for BN=128)
+  constexpr int BPASS = (BN * kBKU + kThreads - 1) / kThreads;
+
+  f32x4 acc[2][NF];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  Unit<P> ga0, ga1, gb[BPASS];
+  auto gload = [&](int st) {
+    const int U = st * kBKU + ua;
+    ga0 = gather<L, P>(rs0, U, args.in_s8);
+    ga1 = gather<L, P>(rs1, U, args.in_s8);
+#pragma unroll
+    for (int p = 0; p < BPASS; ++p) {
+      const int t = tid + p * kThreads;
+      if (t < BN * kBKU) {
+        const int n = t >> 2, u = t & 3;
+        gb[p] = load_unit<P>(W + (long long)(n0 + n) * K + (st * kBKU + u) * 8);
+      }
+    }
+  };
+  auto lstore = [&]() {
+    st_unit<P>(As + ra * S, ua, ga0);
+    st_unit<P>(As + (ra + 64) * S, ua, ga1);
+#pragma unroll
+    for (int p = 0; p < BPASS; ++p) {
+      const int t = tid + p * kThreads;
+      if (t < BN * kBKU) st_unit<P>(Bs + (t >> 2) * S, t & 3, gb[p]);
+    }
+  };
+
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int st = 0; st < NSTAGE; ++st) {
+    if (st + 1 < NSTAGE) gload(st + 1);
+    mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
+    __syncthreads();
+    if (st + 1 < NSTAGE) {
+      lstore();
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows 4*(lane>>4) + q, column lane & 15 of each frag
+  const int col = lane & 15, rq = (lane >> 4) * 4;
+  if constexpr (L < 4) {
+    T* out = reinterpret_cast<T*>(args.out);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const int n = n0 + j * 16 + col;
+        const float b = args.bias[n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long long m = m0 + wave * 32 + i * 16 + rq + q;
+          if (m < args.M) {
+            float v = fmaxf(acc[i][j][q] * args.acc_scale + b, 0.f);
+            st_out<P>(out + m * Geo<L>::N + n, v, args.out_s8);
+          }
+        }
+      }
+  } else {
+    // fc2: Q = acc * scale + b; V = max over the item's A actions
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const int n = j * 16 + col;
+        const float b = n < kMaxA ? args.bias[n] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          Cs[(wave * 32 + i * 16 + rq + q) * 33 + n] = acc[i][j][q] * args.acc_scale + b;
+      }
+    __syncthreads();
+    if (tid < kBM) {
+      const long long m = m0 + tid;
+      if (m < args.M) {
+        const ItemDesc& d = args.desc[m];
+        const float* row = Cs + tid * 33;
+        float v = row[0];
+        for (int a = 1; a < d.A; ++a) v = fmaxf(v, row[a]);
+        args.V[m] = v;
+        if (d.q0_root >= 0)
+          for (int a = 0; a < kMaxA; ++a) args.q0[(long long)d.q0_root * kMaxA + a] = row[a];
+      }
+    }
+  }
+}
+
+template <int L, int P>
+void run_layer(const LayerArgs& a, hipStream_t s) {
+  const long long blocks = (a.M + kBM - 1) / kBM;
+  dim3 grid((unsigned)blocks, Geo<L>::N / Geo<L>::BN);
+  hipLaunchKernelGGL((layer_kernel<L, P>), grid, dim3(kThreads), 0, s, a);
+}
+
+// item descriptors: the 4 frames of each item's stack
+__global__ void item_desc_kernel(long long item_begin, long long n_items, const Seg* __restrict__ segs,
+                                 int nsegs, const RootInfo* __restrict__ roots, FrameBases fb,
+                                 ItemDesc* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  const long long item = item_begin + t;
+  int lo = 0, hi = nsegs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+  }
+  const Seg sg = segs[lo];
+  const RootInfo& ri = roots[sg.root];
+  const long long j = item - sg.item0;
+  ItemDesc d;
+  const int m = sg.level;
+  for (int c = 0; c < 4; ++c) {
+    const int l = m - 3 + c;
+    if (l >= 1) {
+      long long div = 1;
+      for (int q = 0; q < m - l; ++q) div *= sg.A;
+      d.frame[c] = fb.level_frames[l] + (ri.base[l] + j / div) * (long long)kFrameBytes;
+    } else {
+      d.frame[c] = fb.level_frames[0] + ((long long)sg.root * 4 + 3 + l) * (long long)kFrameBytes;
+    }
+  }
+  d.A = sg.A;
+  d.q0_root = sg.kind == 2 ? sg.root : -1;
+  out[t] = d;
+}
+
+template <int P>
+void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V, float* q0,
+              hipStream_t s) {
+  typedef typename PT<P>::T T;
+  T* x1 = reinterpret_cast<T*>(ws);
+  T* x2 = x1 + n * 12800;
+  T* x3 = x2 + n * 5184;
+  T* h = x3 + n * 3136;
+  auto wp = [&](int l) -> const void* {
+    return P == P_FP32 ? (const void*)q.w[l] : P == P_BF16 ? (const void*)q.wb[l] : (const void*)q.w8[l];
+  };
+  // accumulator scales: conv1 sees raw pixels (x 1/255); fp8 undoes both operand scales
+  auto accs = [&](int l) {
+    float s = (P == P_FP8) ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
+    return l == 0 ? s / 255.f : s;
+  };
+  auto outs = [&](int l) { return (P == P_FP8 && l < 4) ? q.ascale[l + 1] : 1.f; };
+  LayerArgs a{};
+  a.desc = desc;
+  a.in_s8 = q.ascale[0];
+  a.M = n * 400; a.in = nullptr; a.w = wp(0); a.bias = q.b[0]; a.acc_scale = accs(0); a.out_s8 = outs(0); a.out = x1;
+  run_layer<0, P>(a, s);
+  a.M = n * 81; a.in = x1; a.w = wp(1); a.bias = q.b[1]; a.acc_scale = accs(1); a.out_s8 = outs(1); a.out = x2;
+  run_layer<1, P>(a, s);
+  a.M = n * 49; a.in = x2; a.w = wp(2); a.bias = q.b[2]; a.acc_scale = accs(2); a.out_s8 = outs(2); a.out = x3;
+  run_layer<2, P>(a, s);
+  a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3); a.out_s8 = outs(3); a.out = h;
+  run_layer<3, P>(a, s);
+  a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
+  run_layer<4, P>(a, s);
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ s, uint16_t* __restrict__ d, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = f2bf(s[i]);
+}
+__global__ void to_fp8_kernel(const float* __restrict__ s, uint8_t* __restrict__ d, long long n, float sc) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = f2e4m3(s[i] * sc);
+}
+__global__ void absmax_kernel(const float* __restrict__ s, long long n, float* out) {
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(s[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned*>(out), __float_as_uint(m));
+}
+
+}  // namespace
+
+size_t qnet_workspace_bytes(long long chunk, int prec) {
+  const size_t el = prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1;
+  return (size_t)chunk * (12800 + 5184 + 3136 + 512) * el + 256;
+}
+
+void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, int nsegs,
+                      const RootInfo* roots, const FrameBases& fb, ItemDesc* out, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s,
+                     item_begin, n_items, segs, nsegs, roots, fb, out);
+}
+
+void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V,
+                 float* q0, hipStream_t s) {
+  if (n <= 0) return;
+  if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, ws, V, q0, s);
+  else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, ws, V, q0, s);
+  else run_qnet<P_FP8>(q, desc, n, ws, V, q0, s);
+}
+
+void launch_convert_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+}
+void launch_convert_fp8(const float* src, uint8_t* dst, long long n, float scale, hipStream_t s) {
+  hipLaunchKernelGGL(to_fp8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, scale);
+}
+void launch_absmax(const float* src, long long n, float* out, hipStream_t s) {
+  long long b = (n + 255) / 256;
+  hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, src, n, out);
+}
+
+}  // namespace bcts

@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: frames, positions and rewards bit-exact; FP32 root vectors within
+1e-5 of the oracle's largest |Q| per root (1e-7 absolute floor); root
+actions equal unless the oracle's best two are within 1e-6 max(1, |max|).
+"""
+import numpy as np
+import pytest
+
+from oracle import qnet as Q, search as S
+from paper_2107_01715_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 0.99
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_01715_amd import bcts
+    return bcts
+
+
+@pytest.fixture(scope="module")
+def setup(lib):
+    ep = W.env_params(1001)
+    w = W.qnet_weights(7)
+    ctx = lib.Context(0)
+    ctx.set_env(ep.delta, ep.vel)
+    ctx.set_qnet(W.qnet_blob(w))
+    world = S.World(ep.delta, ep.vel, Q.prepare(w))
+    yield ctx, world, w
+    ctx.close()
+
+
+def assert_root_parity(q_gpu, act_gpu, ref, A, tag=""):
+    qo = np.asarray(ref.q, dtype=np.float64)
+    err = np.abs(np.asarray(q_gpu[:A], dtype=np.float64) - qo).max()
+    bound = RTOL * np.abs(qo).max() + 1e-7
+    assert err <= bound, f"{tag}: |dQ| {err:.3g} > {bound:.3g}\n gpu {q_gpu[:A]}\n ref {qo}"
+    assert act_gpu == ref.action or act_gpu in ref.ties, f"{tag}: action {act_gpu} vs {ref.action} ties {ref.ties}"
+
+
+@pytest.mark.parametrize("A,d,seed,roots", [(4, 2, 1001, range(0, 64, 9)), (6, 3, 1002, [0, 7]),
+                                            (18, 2, 1003, [3]), (18, 3, 1003, [0]), (2, 6, 5, [1])])
+def test_expansion_bit_exact(lib, setup, A, d, seed, roots):
+    ctx, world, _ = setup
+    pos, st = W.roots(seed, max(roots) + 1)
+    for r in roots:
+        got = ctx.debug_expand(pos[r], st[r], d, A)
+        want = S.enumerate_nodes(world, pos[r], st[r], d, A)
+        for k in range(d):
+            gp, gf, gr = got[k]
+            wp, wf, wr = want[k]
+            assert np.array_equal(gp, wp), f"positions, level {k + 1}"
+            assert np.array_equal(gr, wr), f"rewards, level {k + 1}"
+            bad = np.flatnonzero((gf != wf).reshape(len(gf), -1).any(axis=1))
+            assert bad.size == 0, f"frames differ at level {k + 1} nodes {bad[:8]}"
+
+
+def test_qnet_fp32_matches_oracle(lib, setup):
+    ctx, world, _ = setup
+    _, st = W.roots(11, 40)
+    dense = np.random.default_rng(3).integers(0, 256, size=(9, 4, 84, 84), dtype=np.uint8)
+    x = np.concatenate([st, dense])
+    ctx.set_precision(lib.FP32)
+    for A in (18, 5):
+        got = ctx.debug_qnet(x, A)
+        want = Q.qvalues(x, world.w64, A)
+        err = np.abs(got - want).max(axis=1)
+        bound = RTOL * np.abs(want).max(axis=1) + 1e-6
+        assert (err <= bound).all(), (err / np.abs(want).max(axis=1)).max()
+
+
+@pytest.mark.parametrize("corr_on,c", [(True, 1.0), (False, 1.0), (True, 0.0), (True, 2.5)])
+def test_c1_end_to_end(lib, setup, corr_on, c):
+    """64 roots, A=4, d=2 (the small configuration), FP32."""
+    ctx, world, _ = setup
+    ctx.set_precision(lib.FP32)
+    pos, st = W.roots(1001, 64)
+    act, q = ctx.search(pos, st, 2, 4, GAMMA, lib.correction(corr_on, c))
+    for r in range(64):
+        ref = S.search(world, pos[r], st[r], 2, 4, GAMMA, correction=corr_on, c=c)
+        assert_root_parity(q[r], act[r], ref, 4, f"root {r}")
+
+
+@pytest.mark.parametrize("A,d", [(4, 0), (6, 0), (4, 1), (18, 1), (6, 3), (3, 4), (2, 2)])
+def test_shapes_end_to_end(lib, setup, A, d):
+    ctx, world, _ = setup
+    ctx.set_precision(lib.FP32)
+    pos, st = W.roots(1002 + A + d, 4)
+    act, q = ctx.search(pos, st, d, A, GAMMA, lib.correction(True, 1.0))
+    for r in range(4):
+        ref = S.search(world, pos[r], st[r], d, A, GAMMA, correction=True, c=1.0)
+        assert_root_parity(q[r], act[r], ref, A, f"A={A} d={d} root {r}")
+
+
+def test_exact_gev_mode(lib, setup):
+    ctx, world, _ = setup
+    ctx.set_precision(lib.FP32)
+    pos, st = W.roots(31, 6)
+    act, q = ctx.search(pos, st, 2, 6, GAMMA, lib.correction(True, 1.0, lib.CORR_EXACT_GEV))
+    for r in range(6):
+        ref = S.search(world, pos[r], st[r], 2, 6, GAMMA, correction=True, c=1.0, mode="gev")
+        assert_root_parity(q[r], act[r], ref, 6, f"root {r}")
+
+
+def test_mixed_batch_equals_single(lib, setup):
+    """Roots of different (A, d) in one batch give the single-root results."""
+    ctx, world, _ = setup
+    ctx.set_precision(lib.FP32)
+    n = 24
+    pos, st = W.roots(1004, n)
+    A, d = W.mixed_shapes(1004, n, (4, 6, 18), (0, 1, 2, 3))
+    d = np.where(A == 18, np.minimum(d, 2), d)
+    act, q = ctx.search_batch(pos, st, d, A, GAMMA, lib.correction(True, 1.0))
+    for r in range(n):
+        a1, q1 = ctx.search(pos[r:r + 1], st[r:r + 1], int(d[r]), int(A[r]), GAMMA, lib.correction(True, 1.0))
+        assert act[r] == a1[0]
+        np.testing.assert_array_equal(q[r, :A[r]], q1[0])
+        assert np.all(np.isneginf(q[r, A[r]:]))
+    for r in range(0, n, 5):
+        ref = S.search(world, pos[r], st[r], int(d[r]), int(A[r]), GAMMA, correction=True, c=1.0)
+        assert_root_parity(q[r], act[r], ref, int(A[r]), f"root {r}")
+
+
+def test_device_and_graph_equal_host(lib, setup):
+    import torch
+    ctx, _, _ = setup
+    ctx.set_precision(lib.BF16)
+    n = 16
+    pos, st = W.roots(1006, n)
+    A, d = W.mixed_shapes(1006, n, (4, 6, 18), (1, 2, 3))
+    corr = lib.correction(True, 1.0)
+    act_h, q_h = ctx.search_batch(pos, st, d, A, GAMMA, corr)
+    pt = torch.from_numpy(pos).cuda()
+    stt = torch.from_numpy(st).cuda()
+    at = torch.zeros(n, dtype=torch.int32, device="cuda")
+    qt = torch.zeros(n, 18, dtype=torch.float32, device="cuda")
+    ctx.search_batch_device(pt, stt, d, A, GAMMA, corr, at, qt)
+    torch.cuda.synchronize()
+    assert np.array_equal(at.cpu().numpy(), act_h)
+    assert np.array_equal(qt.cpu().numpy(), q_h)
+    for rep in range(3):
+        qt.zero_()
+        at.fill_(-1)
+        torch.cuda.synchronize()
+        ctx.search_batch_graph(pt, stt, d, A, GAMMA, corr, at, qt, replays=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(at.cpu().numpy(), act_h), rep
+        assert np.array_equal(qt.cpu().numpy(), q_h), rep
+    ctx.set_precision(lib.FP32)
+
+
+@pytest.mark.parametrize("prec,tol", [("BF16", 2e-3), ("FP8", 2e-2)])
+def test_lowp_qnet_matches_emulation(lib, setup, prec, tol):
+    """BF16 / FP8 matrix-core Q-network vs the oracle's emulation of the same
+    operand roundings (FP64 sums, same per-layer scales)."""
+    ctx, world, _ = setup
+    _, st = W.roots(21, 24)
+    dense = np.random.default_rng(8).integers(0, 256, size=(4, 4, 84, 84), dtype=np.uint8)
+    x = np.concatenate([st, dense])
+    if prec == "FP8":
+        _, cal = W.roots(2003, 64)
+        ctx.calibrate_fp8(cal)
+    ctx.set_precision(getattr(lib, prec))
+    got = ctx.debug_qnet(x, 18)
+    ctx.set_precision(lib.FP32)
+    want = Q.qvalues_lowp(x, world.w64, 18, prec.lower(), ascale=ctx.get_fp8_scales())
+    rel = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
+    print(f"{prec} vs emulation: max rel {rel.max():.3g}, mean {rel.mean():.3g}")
+    assert rel.max() < tol, rel.max()
+
+
+@pytest.mark.parametrize("prec,tol", [("BF16", 0.05), ("FP8", 0.6)])
+def test_low_precision_vs_fp64(lib, setup, prec, tol):
+    """Root-vector error and action agreement of BF16 / FP8 searches against
+    the FP64 oracle on the small configuration (reported; loose bound)."""
+    ctx, world, _ = setup
+    pos, st = W.roots(1001, 32)
+    if prec == "FP8":
+        _, cal = W.roots(2003, 64)
+        ctx.calibrate_fp8(cal)
+    ctx.set_precision(getattr(lib, prec))
+    act, q = ctx.search(pos, st, 2, 4, GAMMA, lib.correction(True, 1.0))
+    ctx.set_precision(lib.FP32)
+    errs, agree = [], 0
+    for r in range(32):
+        ref = S.search(world, pos[r], st[r], 2, 4, GAMMA, correction=True, c=1.0)
+        errs.append(np.abs(q[r] - ref.q).max() / np.abs(ref.q).max())
+        agree += act[r] == ref.action or act[r] in ref.ties
+    print(f"{prec}: root-Q rel err max {max(errs):.3g} mean {np.mean(errs):.3g}; agreement {agree}/32")
+    assert max(errs) < tol, max(errs)
+
+
+def test_validation_errors(lib, setup):
+    ctx, _, _ = setup
+    pos, st = W.roots(1, 1)
+    c = lib.correction(True, 1.0)
+    for args in [(2, 19), (2, 0), (7, 4), (-1, 4)]:
+        with pytest.raises(lib.BctsError) as e:
+            ctx.search(pos, st, args[0], args[1], GAMMA, c)
+        assert e.value.status == lib.E_INVAL
+    with pytest.raises(lib.BctsError) as e:          # correction needs A >= 2
+        ctx.search(pos, st, 2, 1, GAMMA, c)
+    assert e.value.status == lib.E_INVAL
+    ctx.search(pos, st, 2, 1, GAMMA, lib.correction(False))   # A = 1 without correction is fine
+    with pytest.raises(lib.BctsError):
+        ctx.search(pos, st, 2, 4, 1.5, c)
+    bad = pos.copy()
+    bad[0, 3, 1] = 84
+    with pytest.raises(lib.BctsError) as e:
+        ctx.search(bad, st, 2, 4, GAMMA, c)
+    assert e.value.status == lib.E_INVAL
+    # the context stays usable
+    ctx.search(pos, st, 1, 4, GAMMA, c)
+
+
+def test_state_errors(lib):
+    ctx = lib.Context(0)
+    pos, st = W.roots(1, 1)
+    with pytest.raises(lib.BctsError) as e:
+        ctx.search(pos, st, 1, 4, GAMMA, lib.correction(True, 1.0))
+    assert e.value.status == lib.E_STATE
+    ctx.close()
