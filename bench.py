@@ -1,0 +1,253 @@
+"""Benchmark: leaf evaluations per second of Batch-BFS search with the BCTS
+correction on one MI355X.
+
+Workload (one step = the whole hot path over one batch, inputs resident in
+HBM): 256 root states, A = 18 actions, depth 3 (5,832 leaves per root,
+1,492,992 per step), gamma = 0.99, correction on with c = 1.0, synthetic sprite
+world and a random Kaiming-initialised Nature-DQN.  Each step expands 3
+levels, scores every leaf (plus the root and depth-1 nodes the correction
+needs), backs up and corrects all 256 roots.
+
+Reported beside the headline (BF16, batched):
+  * the FP8 batched form and the plain FP32 form that searches one root per
+    launch sequence, at the same shape;
+  * root-vector error and root-action agreement against the FP64 oracle (on a
+    sample of roots) and against the FP32 GPU path (all 256 roots);
+  * per-kernel durations from HIP events on the search stream, the roofline of
+    the dominant kernel, p50/p99 step latency;
+  * the FP64 oracle timed on the host cores over a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--precision bf16|fp8|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "leaf evals/sec at A=18,d=3 (BF16/FP8 vs FP32); p50/p99 search latency"
+N_ROOTS, A, DEPTH, GAMMA, C = 256, 18, 3, 0.99, 1.0
+INSTANCE_SEED, WEIGHT_SEED, CALIB_SEED = 1003, 7, 2003
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+HBM_PEAK_GBS = 8000.0
+# algorithmic FLOPs per evaluated stack, by layer (2 * rows * N * K)
+LAYER_FLOPS = {"conv1": 2 * 400 * 32 * 256, "conv2": 2 * 81 * 64 * 512, "conv3": 2 * 49 * 64 * 576,
+               "fc1": 2 * 512 * 3136, "fc2": 2 * A * 512}
+LAYER_KERNEL = {"conv1": "layer_kernel<0,P>", "conv2": "layer_kernel<1,P>", "conv3": "layer_kernel<2,P>",
+                "fc1": "layer_kernel<3,P>", "fc2": "layer_kernel<4,P>"}
+# algorithmic bytes per new node written by the expansion: frame, positions, return, reward
+EXPAND_BYTES_PER_NODE = 7056 + 16 + 4 + 1
+
+
+def _oracle_root(args):
+    """One root of the workload through the FP64 oracle (CPU worker)."""
+    r, = args
+    from threadpoolctl import threadpool_limits
+    from paper_2107_01715_amd import workload as W
+    from oracle import qnet as Q, search as S
+    with threadpool_limits(1):
+        ep = W.env_params(INSTANCE_SEED)
+        world = S.World(ep.delta, ep.vel, Q.prepare(W.qnet_weights(WEIGHT_SEED)))
+        pos, st = W.roots(INSTANCE_SEED, r + 1)
+        res = S.search(world, pos[r], st[r], DEPTH, A, GAMMA, correction=True, c=C)
+        return r, res.q, res.action, res.ties
+
+
+def cpu_baseline(n_sample: int):
+    """The oracle as it stands on a bounded sample of roots, one process per
+    core (fork, before any GPU use)."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16, n_sample)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        out = pool.map(_oracle_root, [(r,) for r in range(n_sample)])
+    dt = time.perf_counter() - t0
+    leaves = n_sample * A ** DEPTH
+    return {"value": leaves / dt, "unit": "leaf evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_sample} roots of the A=18,d=3 workload ({leaves} leaves), FP64, "
+                      f"{dt:.1f} s wall"}, {r: (q, a, t) for r, q, a, t in out}
+
+
+def agreement(act, q, ref):
+    """Per-root error (|dQ|max / |Q|max) and tie-excused action agreement."""
+    import numpy as np
+    errs, agree = [], 0
+    for r, (qo, ao, ties) in ref.items():
+        errs.append(float(np.abs(q[r, :A] - qo).max() / np.abs(qo).max()))
+        agree += int(act[r] == ao or act[r] in ties)
+    return {"roots": len(ref), "agree": agree, "rate": agree / len(ref),
+            "max_rel_err": max(errs), "mean_rel_err": float(np.mean(errs))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32"])
+    ap.add_argument("--cpu-sample", type=int, default=16, help="roots timed through the oracle (0 = skip)")
+    ap.add_argument("--skip-fp32-single", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the search shards over roots "
+              f"with no communication; see DESIGN.md for the multi-GPU layout)", file=sys.stderr)
+        sys.exit(2)
+
+    # CPU baseline first: the worker pool forks before the GPU is touched
+    cpu, oracle_ref = (None, {})
+    if args.cpu_sample > 0:
+        cpu, oracle_ref = cpu_baseline(args.cpu_sample)
+        print(f"# cpu baseline: {cpu['value']:.1f} leaf evals/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+    from paper_2107_01715_amd import bcts, workload as W
+
+    ep = W.env_params(INSTANCE_SEED)
+    pos, st = W.roots(INSTANCE_SEED, N_ROOTS)
+    _, cal = W.roots(CALIB_SEED, 64)
+    ctx = bcts.Context(0)
+    ctx.set_env(ep.delta, ep.vel)
+    ctx.set_qnet(W.qnet_blob(W.qnet_weights(WEIGHT_SEED)))
+    ctx.calibrate_fp8(cal)
+    corr = bcts.correction(True, C)
+    dev = torch.device("cuda:0")
+    pos_t = torch.from_numpy(pos).to(dev)
+    st_t = torch.from_numpy(st).to(dev)
+    act_t = torch.zeros(N_ROOTS, dtype=torch.int32, device=dev)
+    q_t = torch.zeros(N_ROOTS, 18, dtype=torch.float32, device=dev)
+    depth = np.full(N_ROOTS, DEPTH, np.int32)
+    Av = np.full(N_ROOTS, A, np.int32)
+    stream = torch.cuda.Stream()
+    leaves = N_ROOTS * A ** DEPTH
+    prec_id = {"fp32": bcts.FP32, "bf16": bcts.BF16, "fp8": bcts.FP8}
+
+    def batched(prec, steps, warmup, timed=True):
+        ctx.set_precision(prec_id[prec])
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                ctx.search_batch_device(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, stream=stream)
+            torch.cuda.synchronize()
+            ctx.set_timing(timed)
+            per_step, kern = [], np.zeros(24)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.search_batch_device(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, stream=stream)
+                if timed:
+                    tm = ctx.get_timing()
+                    per_step.append(tm[3])
+                    kern += tm
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ctx.set_timing(False)
+        return wall, per_step, kern / max(steps, 1), act_t.cpu().numpy().copy(), q_t.cpu().numpy().copy()
+
+    print(f"# {args.precision} batched: warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
+    wall, per_step, kern, act_main, q_main = batched(args.precision, args.steps, args.warmup)
+    ms_step = wall / args.steps * 1e3
+    value = leaves / (wall / args.steps)
+
+    results = {args.precision: (value, act_main, q_main, kern, per_step)}
+    for prec in ("bf16", "fp8", "fp32"):
+        if prec in results:
+            continue
+        if prec == "fp32":
+            w2, ps2, k2, a2, q2 = batched(prec, 1, 1)
+            results[prec] = (leaves / w2, a2, q2, k2, ps2)
+        else:
+            w2, ps2, k2, a2, q2 = batched(prec, max(3, args.steps // 2), 1)
+            results[prec] = (leaves / (w2 / max(3, args.steps // 2)), a2, q2, k2, ps2)
+        print(f"# {prec} batched: {results[prec][0]:.4g} leaf evals/s", file=sys.stderr, flush=True)
+
+    # the plain form: FP32, one root per launch sequence
+    single = None
+    if not args.skip_fp32_single:
+        ctx.set_precision(bcts.FP32)
+        one_d, one_a = depth[:1], Av[:1]
+        with torch.cuda.stream(stream):
+            ctx.search_batch_device(pos_t[:1], st_t[:1], one_d, one_a, GAMMA, corr, act_t[:1], q_t[:1], stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r in range(N_ROOTS):
+                ctx.search_batch_device(pos_t[r:r + 1], st_t[r:r + 1], one_d, one_a, GAMMA, corr,
+                                        act_t[r:r + 1], q_t[r:r + 1], stream=stream)
+            torch.cuda.synchronize()
+            w1 = time.perf_counter() - t0
+        single = {"value": leaves / w1, "ms_per_pass": w1 * 1e3, "dtype": "f32",
+                  "form": "one root per launch sequence, 256 sequential searches"}
+        print(f"# fp32 single-root: {single['value']:.4g} leaf evals/s", file=sys.stderr, flush=True)
+
+    # accuracy: vs FP64 oracle on the sample, vs FP32 GPU path on all roots
+    a32, q32 = results["fp32"][1], results["fp32"][2]
+    gpu32_ref = {}
+    for r in range(N_ROOTS):
+        qq = q32[r, :A].astype(np.float64)
+        m = qq.max()
+        ties = [int(i) for i in np.flatnonzero(qq >= m - 1e-6 * max(1.0, abs(m)))]
+        gpu32_ref[r] = (qq, int(a32[r]), ties)
+    accuracy = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        _, a_, q_, _, _ = results[prec]
+        accuracy[prec] = {}
+        if oracle_ref:
+            accuracy[prec]["vs_fp64_oracle"] = agreement(a_, q_, oracle_ref)
+        if prec != "fp32":
+            accuracy[prec]["vs_fp32_gpu"] = agreement(a_, q_, gpu32_ref)
+
+    # per-kernel roofline of the headline precision
+    n_items = kern[16]
+    kernels = {}
+    for i, name in enumerate(("conv1", "conv2", "conv3", "fc1", "fc2")):
+        ms = kern[4 + i]
+        launches = kern[9]
+        flops = LAYER_FLOPS[name] * n_items
+        kernels[name] = {"ms_per_step": ms, "launches": launches, "avg_launch_ms": ms / max(launches, 1),
+                         "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    ach = kernels[dom]["tflops"]
+    peak = PEAK_TFLOPS[args.precision]
+    exp_nodes = kern[17]
+    exp_ms = kern[0]
+    exp_gbs = exp_nodes * EXPAND_BYTES_PER_NODE / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else None
+    qnet_tflops = leaves * sum(LAYER_FLOPS.values()) / (kern[1] * 1e-3) / 1e12 if kern[1] > 0 else None
+    roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision), "layer": dom,
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "flop_per_launch": LAYER_FLOPS[dom] * n_items / max(kern[9], 1),
+                "avg_launch_ms": kernels[dom]["avg_launch_ms"], "traffic": None}
+
+    lat = np.array(per_step) if per_step else np.array([ms_step])
+    out = {
+        "metric": METRIC, "value": value, "unit": "leaf evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16": "bf16", "fp8": "fp8_e4m3", "fp32": "f32"}[args.precision],
+        "data": "synthetic (seeded sprite world, random Kaiming-uniform Nature-DQN)",
+        "config": {"workload": "256 roots, A=18, depth 3 (5832 leaves/root), gamma 0.99, BCTS c=1.0, "
+                               "all roots in one batched launch sequence", "roots": N_ROOTS, "A": A,
+                   "depth": DEPTH, "leaves_per_step": leaves, "q_evals_per_step": int(n_items),
+                   "precision": args.precision},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "whole-batch search latency per step (HIP events)"},
+        "precisions": {p: {"value": results[p][0]} for p in results},
+        "fp32_single_root": single,
+        "speedup_vs_fp32_single_root": (value / single["value"]) if single else None,
+        "accuracy": accuracy,
+        "stages_ms": {"expand": kern[0], "qnet": kern[1], "backup_correct": kern[2], "total": kern[3]},
+        "kernels": kernels,
+        "qnet_stage_tflops": qnet_tflops,
+        "expand": {"bound": "hbm", "achieved": exp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": exp_gbs / HBM_PEAK_GBS if exp_gbs else None, "nodes": exp_nodes,
+                   "bytes_per_node": EXPAND_BYTES_PER_NODE},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

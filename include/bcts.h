@@ -201,11 +201,16 @@ bcts_status bcts_debug_expand(bcts_ctx* ctx, const int32_t* pos, const uint8_t* 
 /* Q-network on n host stacks at the current precision: out_q float [n][A]. */
 bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
                             float* out_q);
-/* Average duration (ms) of each stage kernel over the last search on ctx:
- * out[0] expansion, out[1] leaf Q-network, out[2] backup + correction,
- * out[3] whole search; measured with HIP events when timing is enabled.    */
+/* Kernel timing with HIP events on the search's own stream.  While enabled,
+ * every search (host, device or graph form) records events around its
+ * launches and waits for them; bcts_get_timing then reports the last search:
+ *   out[0] expansion ms, out[1] Q-network ms, out[2] backup+correction ms,
+ *   out[3] whole search ms, out[4..8] conv1/conv2/conv3/fc1/fc2 ms summed over
+ *   chunks, out[9] chunks (launches per layer), out[10..15] expansion ms of
+ *   levels 1..6, out[16] Q-network items, out[17] expanded nodes.
+ * A graph replay fills only out[3] (ms per replay).  out has 24 doubles.    */
 bcts_status bcts_set_timing(bcts_ctx* ctx, int32_t enabled);
-bcts_status bcts_get_timing(bcts_ctx* ctx, double* out4);
+bcts_status bcts_get_timing(bcts_ctx* ctx, double* out24);
 
 #ifdef __cplusplus
 }

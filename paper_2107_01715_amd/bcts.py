@@ -277,7 +277,7 @@ def bcts_set_timing(ctx, enabled: bool):
 
 
 def bcts_get_timing(ctx) -> np.ndarray:
-    out = np.zeros(4, np.float64)
+    out = np.zeros(24, np.float64)
     _check(ctx, _get_timing(ctx, _ptr(out)))
     return out
 

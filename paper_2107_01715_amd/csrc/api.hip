@@ -111,10 +111,13 @@ struct bcts_ctx {
   // pinned staging for tables and host I/O
   char* pinned = nullptr;
   size_t pinned_bytes = 0;
-  // timing
+  // timing: events of the last timed search (see collect_timing)
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  double t_ms[4] = {0, 0, 0, 0};
+  std::vector<hipEvent_t> tev;      // [start, level 1..maxd, chunk x 6, qnet end, end]
+  int t_maxd = 0, t_chunks = 0;
+  long long t_items = 0, t_nodes = 0;
+  double t_ms[24] = {0};
   // serving
   struct ServeEngine* serve = nullptr;
 };
@@ -325,11 +328,32 @@ bcts_status upload_tables(bcts_ctx* c, const Plan& p, hipStream_t s) {
 
 // Enqueue the kernels of a planned search.  Root inputs and outputs are
 // device pointers.
+bcts_status ensure_events(bcts_ctx* c, size_t n) {
+  while (c->tev.size() < n) {
+    hipEvent_t e;
+    HIPCHECK(c, hipEventCreate(&e));
+    c->tev.push_back(e);
+  }
+  return BCTS_OK;
+}
+
 bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t* d_pos,
                               const uint8_t* d_stacks, float gamma, float corr_scale, int32_t* d_act,
                               float* d_q, hipStream_t s, bool timed) {
   const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
-  if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
+  const int nchunks = (int)((p.n_items + p.chunk - 1) / p.chunk);
+  hipEvent_t* ev = nullptr;
+  if (timed) {
+    bcts_status st = ensure_events(c, (size_t)(3 + p.maxd + 6 * nchunks));
+    if (st != BCTS_OK) return st;
+    ev = c->tev.data();
+    c->t_maxd = p.maxd;
+    c->t_chunks = nchunks;
+    c->t_items = p.n_items;
+    c->t_nodes = 0;
+    for (int k = 1; k <= p.maxd; ++k) c->t_nodes += p.lvl_count[k];
+    HIPCHECK(c, hipEventRecord(ev[0], s));
+  }
   double g = 1.0;
   for (int k = 1; k <= p.maxd; ++k) {
     LevelRoots lr{reinterpret_cast<const int*>(A + p.o_lroot[k]),
@@ -339,25 +363,26 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
                   k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr, c->env, (float)g,
                   reinterpret_cast<uint8_t*>(A + p.o_pos[k]), reinterpret_cast<uint8_t*>(A + p.o_frames[k]),
                   reinterpret_cast<float*>(A + p.o_ret[k]), reinterpret_cast<uint8_t*>(A + p.o_rew[k]), s);
+    if (timed) HIPCHECK(c, hipEventRecord(ev[k], s));
     g *= gamma;
   }
-  if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
   FrameBases fb{};
   fb.level_frames[0] = d_stacks;
   for (int k = 1; k <= p.maxd; ++k) fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
   ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
   float* V = reinterpret_cast<float*>(A + p.o_V);
   float* q0 = reinterpret_cast<float*>(A + p.o_q0);
-  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk) {
+  int ci = 0;
+  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk, ++ci) {
     const long long cnt = std::min(p.chunk, p.n_items - i0);
     launch_item_desc(i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
-    launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + i0, q0, s);
+    launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + i0, q0, s, timed ? ev + 1 + p.maxd + 6 * ci : nullptr);
   }
-  if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+  if (timed) HIPCHECK(c, hipEventRecord(ev[1 + p.maxd + 6 * nchunks], s));
   LevelRet lr{};
   for (int k = 1; k <= p.maxd; ++k) lr.ret[k] = reinterpret_cast<const float*>(A + p.o_ret[k]);
   launch_backup_correct(p.n, roots, V, q0, lr, gamma, corr_scale, d_act, d_q, s);
-  if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
+  if (timed) HIPCHECK(c, hipEventRecord(ev[2 + p.maxd + 6 * nchunks], s));
   HIPCHECK(c, hipGetLastError());
   return BCTS_OK;
 }
@@ -368,14 +393,31 @@ bcts_status enqueue_search(bcts_ctx* c, const Plan& p, const int32_t* d_pos, con
   return enqueue_search_at(c, p, c->arena, d_pos, d_stacks, gamma, corr_scale, d_act, d_q, s, timed);
 }
 
+// Per-stage and per-kernel durations of the last timed search:
+// [0] expansion, [1] Q-network, [2] backup + correction, [3] total (ms);
+// [4..8] conv1, conv2, conv3, fc1, fc2 summed over chunks (ms); [9] chunks;
+// [10..15] expansion of levels 1..6 (ms); [16] eval items; [17] new nodes.
 bcts_status collect_timing(bcts_ctx* c) {
-  HIPCHECK(c, hipEventSynchronize(c->ev[3]));
-  float a, b, d, e;
-  HIPCHECK(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
-  HIPCHECK(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
-  HIPCHECK(c, hipEventElapsedTime(&d, c->ev[2], c->ev[3]));
-  HIPCHECK(c, hipEventElapsedTime(&e, c->ev[0], c->ev[3]));
-  c->t_ms[0] = a; c->t_ms[1] = b; c->t_ms[2] = d; c->t_ms[3] = e;
+  const int D = c->t_maxd, C = c->t_chunks;
+  hipEvent_t* ev = c->tev.data();
+  const int q_end = 1 + D + 6 * C, end = q_end + 1;
+  HIPCHECK(c, hipEventSynchronize(ev[end]));
+  auto el = [&](int a, int b) -> double {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return -1.0;
+    return ms;
+  };
+  for (double& v : c->t_ms) v = 0.0;
+  c->t_ms[0] = el(0, D);
+  c->t_ms[1] = el(D, q_end);
+  c->t_ms[2] = el(q_end, end);
+  c->t_ms[3] = el(0, end);
+  for (int ci = 0; ci < C; ++ci)
+    for (int l = 0; l < 5; ++l) c->t_ms[4 + l] += el(1 + D + 6 * ci + l, 1 + D + 6 * ci + l + 1);
+  c->t_ms[9] = C;
+  for (int k = 1; k <= D; ++k) c->t_ms[9 + k] = el(k - 1, k);
+  c->t_ms[16] = (double)c->t_items;
+  c->t_ms[17] = (double)c->t_nodes;
   return BCTS_OK;
 }
 
@@ -670,6 +712,7 @@ void bcts_destroy(bcts_ctx* c) {
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -949,7 +992,7 @@ bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos
   if (c->timing) {
     float ms = 0.f;
     HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
-    c->t_ms[0] = c->t_ms[1] = c->t_ms[2] = 0.0;
+    for (double& v : c->t_ms) v = 0.0;
     c->t_ms[3] = ms / replays;
   }
   return BCTS_OK;
@@ -1123,9 +1166,9 @@ bcts_status bcts_set_timing(bcts_ctx* c, int32_t enabled) {
   return BCTS_OK;
 }
 
-bcts_status bcts_get_timing(bcts_ctx* c, double* out4) {
-  if (!c || !out4) return BCTS_E_INVAL;
-  for (int i = 0; i < 4; ++i) out4[i] = c->t_ms[i];
+bcts_status bcts_get_timing(bcts_ctx* c, double* out24) {
+  if (!c || !out24) return BCTS_E_INVAL;
+  for (int i = 0; i < 24; ++i) out24[i] = c->t_ms[i];
   return BCTS_OK;
 }
 

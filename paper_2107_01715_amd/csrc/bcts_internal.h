@@ -100,9 +100,11 @@ void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, 
 
 // Q-network over a chunk of items (descs already built): writes V[item] and
 // q0 rows.  `ws` is a workspace of qnet_workspace_bytes(chunk, prec) bytes.
+// With `ev` (6 events) the launches are bracketed: ev[0] before conv1,
+// ev[l+1] after layer l.
 size_t qnet_workspace_bytes(long long chunk, int prec);
 void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
-                 void* ws, float* V, float* q0, hipStream_t s);
+                 void* ws, float* V, float* q0, hipStream_t s, hipEvent_t* ev = nullptr);
 
 struct LevelRet {
   const float* ret[kMaxD + 1];   // ret_k per level (index 0 unused)

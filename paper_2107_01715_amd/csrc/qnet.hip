@@ -434,7 +434,7 @@ __global__ void item_desc_kernel(long long item_begin, long long n_items, const 
 
 template <int P>
 void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V, float* q0,
-              hipStream_t s) {
+              hipStream_t s, hipEvent_t* ev) {
   typedef typename PT<P>::T T;
   T* x1 = reinterpret_cast<T*>(ws);
   T* x2 = x1 + n * 12800;
@@ -451,17 +451,23 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, flo
   auto outs = [&](int l) { return (P == P_FP8 && l < 4) ? q.ascale[l + 1] : 1.f; };
   LayerArgs a{};
   a.desc = desc;
+  if (ev) (void)hipEventRecord(ev[0], s);
   a.in_s8 = q.ascale[0];
   a.M = n * 400; a.in = nullptr; a.w = wp(0); a.bias = q.b[0]; a.acc_scale = accs(0); a.out_s8 = outs(0); a.out = x1;
   run_layer<0, P>(a, s);
+  if (ev) (void)hipEventRecord(ev[1], s);
   a.M = n * 81; a.in = x1; a.w = wp(1); a.bias = q.b[1]; a.acc_scale = accs(1); a.out_s8 = outs(1); a.out = x2;
   run_layer<1, P>(a, s);
+  if (ev) (void)hipEventRecord(ev[2], s);
   a.M = n * 49; a.in = x2; a.w = wp(2); a.bias = q.b[2]; a.acc_scale = accs(2); a.out_s8 = outs(2); a.out = x3;
   run_layer<2, P>(a, s);
+  if (ev) (void)hipEventRecord(ev[3], s);
   a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3); a.out_s8 = outs(3); a.out = h;
   run_layer<3, P>(a, s);
+  if (ev) (void)hipEventRecord(ev[4], s);
   a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
   run_layer<4, P>(a, s);
+  if (ev) (void)hipEventRecord(ev[5], s);
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ s, uint16_t* __restrict__ d, long long n) {
@@ -496,11 +502,11 @@ void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, 
 }
 
 void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V,
-                 float* q0, hipStream_t s) {
+                 float* q0, hipStream_t s, hipEvent_t* ev) {
   if (n <= 0) return;
-  if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, ws, V, q0, s);
-  else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, ws, V, q0, s);
-  else run_qnet<P_FP8>(q, desc, n, ws, V, q0, s);
+  if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, ws, V, q0, s, ev);
+  else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, ws, V, q0, s, ev);
+  else run_qnet<P_FP8>(q, desc, n, ws, V, q0, s, ev);
 }
 
 void launch_convert_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) {

@@ -156,10 +156,13 @@ def test_device_and_graph_equal_host(lib, setup):
     ctx.set_precision(lib.FP32)
 
 
-@pytest.mark.parametrize("prec,tol", [("BF16", 2e-3), ("FP8", 2e-2)])
-def test_lowp_qnet_matches_emulation(lib, setup, prec, tol):
+@pytest.mark.parametrize("prec,tol,tol_med", [("BF16", 2e-3, 1e-4), ("FP8", 5e-2, 1e-3)])
+def test_lowp_qnet_matches_emulation(lib, setup, prec, tol, tol_med):
     """BF16 / FP8 matrix-core Q-network vs the oracle's emulation of the same
-    operand roundings (FP64 sums, same per-layer scales)."""
+    operand roundings (FP64 sums, same per-layer scales).  An activation whose
+    FP32 value sits at a rounding boundary may round the other way than in
+    the FP64 emulation (one e4m3 step is 12.5%), so most stacks agree to FP32
+    rounding (the median bound) and a few differ by such a flip (the max)."""
     ctx, world, _ = setup
     _, st = W.roots(21, 24)
     dense = np.random.default_rng(8).integers(0, 256, size=(4, 4, 84, 84), dtype=np.uint8)
@@ -172,14 +175,18 @@ def test_lowp_qnet_matches_emulation(lib, setup, prec, tol):
     ctx.set_precision(lib.FP32)
     want = Q.qvalues_lowp(x, world.w64, 18, prec.lower(), ascale=ctx.get_fp8_scales())
     rel = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
-    print(f"{prec} vs emulation: max rel {rel.max():.3g}, mean {rel.mean():.3g}")
+    print(f"{prec} vs emulation: max rel {rel.max():.3g}, median {np.median(rel):.3g}")
     assert rel.max() < tol, rel.max()
+    assert np.median(rel) < tol_med, np.median(rel)
 
 
-@pytest.mark.parametrize("prec,tol", [("BF16", 0.05), ("FP8", 0.6)])
-def test_low_precision_vs_fp64(lib, setup, prec, tol):
+@pytest.mark.parametrize("prec,tol_mean,min_agree", [("BF16", 0.01, 31), ("FP8", 0.25, 24)])
+def test_low_precision_vs_fp64(lib, setup, prec, tol_mean, min_agree):
     """Root-vector error and action agreement of BF16 / FP8 searches against
-    the FP64 oracle on the small configuration (reported; loose bound)."""
+    the FP64 oracle on the small configuration (reported; loose bounds: the
+    error is that of the operand precision itself -- the emulation test above
+    checks the kernels against the same roundings).  Errors are relative to
+    the root's largest |Q|, so roots whose values are all near 0 read large."""
     ctx, world, _ = setup
     pos, st = W.roots(1001, 32)
     if prec == "FP8":
@@ -194,7 +201,8 @@ def test_low_precision_vs_fp64(lib, setup, prec, tol):
         errs.append(np.abs(q[r] - ref.q).max() / np.abs(ref.q).max())
         agree += act[r] == ref.action or act[r] in ref.ties
     print(f"{prec}: root-Q rel err max {max(errs):.3g} mean {np.mean(errs):.3g}; agreement {agree}/32")
-    assert max(errs) < tol, max(errs)
+    assert np.mean(errs) < tol_mean, np.mean(errs)
+    assert agree >= min_agree, agree
 
 
 def test_validation_errors(lib, setup):
