@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 LAYER_FLOPS = {"conv1": 2 * 400 * 32 * 256, "conv2": 2 * 81 * 64 * 512, "conv3": 2 * 49 * 64 * 576,
                "fc1": 2 * 512 * 3136, "fc2": 2 * A * 512}
 LAYER_KERNEL = {"conv1": "layer_kernel<0,P>", "conv2": "layer_kernel<1,P>", "conv3": "layer_kernel<2,P>",
-                "fc1": "layer_kernel<3,P>", "fc2": "layer_kernel<4,P>"}
+                "fc1": "layer_kernel<3,P>", "fc2": "layer_kernel<4,P>", "conv_fused": "conv_fused_kernel<P,T>"}
 # algorithmic bytes per new node written by the expansion: frame, positions, return, reward
 EXPAND_BYTES_PER_NODE = 7056 + 16 + 4 + 1
 
@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="roots timed through the oracle (0 = skip)")
     ap.add_argument("--skip-fp32-single", action="store_true")
+    ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
+    ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline precision only (no comparison forms, no accuracy): for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the search shards over roots "
@@ -128,7 +132,7 @@ def main():
     prec_id = {"fp32": bcts.FP32, "bf16": bcts.BF16, "fp8": bcts.FP8}
 
     def batched(prec, steps, warmup, timed=True):
-        ctx.set_precision(prec_id[prec])
+        set_prec(prec)
         with torch.cuda.stream(stream):
             for _ in range(warmup):
                 ctx.search_batch_device(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, stream=stream)
@@ -147,13 +151,52 @@ def main():
             ctx.set_timing(False)
         return wall, per_step, kern / max(steps, 1), act_t.cpu().numpy().copy(), q_t.cpu().numpy().copy()
 
+    # autotune the Q-network launch shape per precision (cached by shape)
+    tuned_all = {}
+    for prec in ((args.precision,) if args.quick else ("bf16", "fp8")):
+        if prec == "fp32":
+            continue
+        ctx.set_precision(prec_id[prec])
+        key = f"{prec}:{N_ROOTS}x{A}^{DEPTH}"
+        cache = {}
+        try:
+            cache = json.load(open(args.tune_cache))
+        except (OSError, ValueError):
+            pass
+        if key in cache and not args.retune:
+            best = cache[key]
+            ctx.set_tuning(bcts.TUNE_FUSED, best["fused"])
+            ctx.set_tuning(bcts.TUNE_FUSED_ROUND, best["round"])
+            ctx.set_tuning(bcts.TUNE_FUSED_CHUNK, best["chunk"])
+        else:
+            with torch.cuda.stream(stream):
+                best = ctx.autotune(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, reps=2, stream=stream)
+            torch.cuda.synchronize()
+            cache[key] = best
+            try:
+                json.dump(cache, open(args.tune_cache, "w"))
+            except OSError:
+                pass
+        tuned_all[prec] = {k: best[k] for k in ("fused", "round", "chunk")}
+        tuned_all[prec]["us_per_search"] = best.get("us_per_search")
+        print(f"# autotune {prec}: {best}", file=sys.stderr, flush=True)
+    tuned = tuned_all.get(args.precision, {})
+
+    def set_prec(prec):
+        ctx.set_precision(prec_id[prec])
+        if prec in tuned_all:
+            t = tuned_all[prec]
+            ctx.set_tuning(bcts.TUNE_FUSED, t["fused"])
+            ctx.set_tuning(bcts.TUNE_FUSED_ROUND, t["round"])
+            ctx.set_tuning(bcts.TUNE_FUSED_CHUNK, t["chunk"])
+
     print(f"# {args.precision} batched: warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
     wall, per_step, kern, act_main, q_main = batched(args.precision, args.steps, args.warmup)
     ms_step = wall / args.steps * 1e3
     value = leaves / (wall / args.steps)
 
     results = {args.precision: (value, act_main, q_main, kern, per_step)}
-    for prec in ("bf16", "fp8", "fp32"):
+    for prec in (() if args.quick else ("bf16", "fp8", "fp32")):
         if prec in results:
             continue
         if prec == "fp32":
@@ -166,7 +209,7 @@ def main():
 
     # the plain form: FP32, one root per launch sequence
     single = None
-    if not args.skip_fp32_single:
+    if not args.skip_fp32_single and not args.quick:
         ctx.set_precision(bcts.FP32)
         one_d, one_a = depth[:1], Av[:1]
         with torch.cuda.stream(stream):
@@ -183,6 +226,9 @@ def main():
         print(f"# fp32 single-root: {single['value']:.4g} leaf evals/s", file=sys.stderr, flush=True)
 
     # accuracy: vs FP64 oracle on the sample, vs FP32 GPU path on all roots
+    accuracy = {}
+    if "fp32" not in results:
+        results["fp32"] = results[args.precision]
     a32, q32 = results["fp32"][1], results["fp32"][2]
     gpu32_ref = {}
     for r in range(N_ROOTS):
@@ -190,8 +236,7 @@ def main():
         m = qq.max()
         ties = [int(i) for i in np.flatnonzero(qq >= m - 1e-6 * max(1.0, abs(m)))]
         gpu32_ref[r] = (qq, int(a32[r]), ties)
-    accuracy = {}
-    for prec in ("fp32", "bf16", "fp8"):
+    for prec in (() if args.quick else ("fp32", "bf16", "fp8")):
         _, a_, q_, _, _ = results[prec]
         accuracy[prec] = {}
         if oracle_ref:
@@ -201,13 +246,20 @@ def main():
 
     # per-kernel roofline of the headline precision
     n_items = kern[16]
+    fused = kern[18] > 0.5
+    names = ("conv_fused", None, None, "fc1", "fc2") if fused else ("conv1", "conv2", "conv3", "fc1", "fc2")
+    flops_of = dict(LAYER_FLOPS)
+    flops_of["conv_fused"] = LAYER_FLOPS["conv1"] + LAYER_FLOPS["conv2"] + LAYER_FLOPS["conv3"]
     kernels = {}
-    for i, name in enumerate(("conv1", "conv2", "conv3", "fc1", "fc2")):
+    for i, name in enumerate(names):
+        if name is None:
+            continue
         ms = kern[4 + i]
         launches = kern[9]
-        flops = LAYER_FLOPS[name] * n_items
+        flops = flops_of[name] * n_items
         kernels[name] = {"ms_per_step": ms, "launches": launches, "avg_launch_ms": ms / max(launches, 1),
-                         "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else None}
+                         "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else None,
+                         "algorithmic_flop_per_stack": flops_of[name]}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     ach = kernels[dom]["tflops"]
     peak = PEAK_TFLOPS[args.precision]
@@ -215,9 +267,9 @@ def main():
     exp_ms = kern[0]
     exp_gbs = exp_nodes * EXPAND_BYTES_PER_NODE / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else None
     qnet_tflops = leaves * sum(LAYER_FLOPS.values()) / (kern[1] * 1e-3) / 1e12 if kern[1] > 0 else None
-    roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision), "layer": dom,
-                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "flop_per_launch": LAYER_FLOPS[dom] * n_items / max(kern[9], 1),
+    roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision).replace("T", str(tuned.get("round", ""))),
+                "layer": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "flop_per_launch": flops_of[dom] * n_items / max(kern[9], 1),
                 "avg_launch_ms": kernels[dom]["avg_launch_ms"], "traffic": None}
 
     lat = np.array(per_step) if per_step else np.array([ms_step])
@@ -236,6 +288,7 @@ def main():
         "fp32_single_root": single,
         "speedup_vs_fp32_single_root": (value / single["value"]) if single else None,
         "accuracy": accuracy,
+        "autotuned": tuned_all,
         "stages_ms": {"expand": kern[0], "qnet": kern[1], "backup_correct": kern[2], "total": kern[3]},
         "kernels": kernels,
         "qnet_stage_tflops": qnet_tflops,

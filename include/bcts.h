@@ -172,6 +172,34 @@ bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_
                                     int32_t* d_out_action, float* d_out_q, int32_t replays,
                                     void* hip_stream);
 
+/* ---- tuning -------------------------------------------------------------- */
+/* Q-network execution choices (none changes results beyond the operand
+ * precision; every choice keeps each stack's sum order fixed):
+ *   BCTS_TUNE_FUSED        1 = BF16/FP8 run conv1..conv3 fused per sibling
+ *                          group (default), 0 = layer-by-layer kernels
+ *   BCTS_TUNE_FUSED_ROUND  stacks per LDS round of the fused kernel: 1..4
+ *                          (BF16 caps at 3: a round of 4 exceeds the LDS)
+ *   BCTS_TUNE_FUSED_CHUNK  stacks per Q-network chunk on the fused path
+ *   BCTS_TUNE_LAYER_CHUNK  stacks per chunk on the layer-by-layer path    */
+typedef enum {
+  BCTS_TUNE_FUSED = 0,
+  BCTS_TUNE_FUSED_ROUND = 1,
+  BCTS_TUNE_FUSED_CHUNK = 2,
+  BCTS_TUNE_LAYER_CHUNK = 3
+} bcts_tune_key;
+bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
+bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);
+/* Autotuner: times every candidate (fused or not, round 1..4, chunk 256Ki /
+ * 1Mi stacks) on one device batch (arguments as in
+ * bcts_search_batch_device; the scratch outputs receive the results),
+ * `reps` timed searches each after one warm-up, keeps the fastest setting
+ * on the context and returns it: out_best = {fused, round, chunk,
+ * microseconds per search}.  Candidates over the HBM budget are skipped.   */
+bcts_status bcts_autotune(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos, const uint8_t* d_stacks,
+                          const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                          void* d_scratch_action, void* d_scratch_q, int32_t reps, void* hip_stream,
+                          int64_t* out_best);
+
 /* ---- serving: continuous batching with HBM-budget admission ------------ */
 /* Queue one request (host buffers copied).  Returns a ticket.  Requests
  * whose own minimal footprint exceeds the budget fail with BCTS_E_NOMEM.   */
@@ -207,7 +235,8 @@ bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int
  *   out[0] expansion ms, out[1] Q-network ms, out[2] backup+correction ms,
  *   out[3] whole search ms, out[4..8] conv1/conv2/conv3/fc1/fc2 ms summed over
  *   chunks, out[9] chunks (launches per layer), out[10..15] expansion ms of
- *   levels 1..6, out[16] Q-network items, out[17] expanded nodes.
+ *   levels 1..6, out[16] Q-network items, out[17] expanded nodes, out[18] 1 if
+ *   the fused conv kernel ran (its time is then in out[4]; out[5..6] are 0).
  * A graph replay fills only out[3] (ms per replay).  out has 24 doubles.    */
 bcts_status bcts_set_timing(bcts_ctx* ctx, int32_t enabled);
 bcts_status bcts_get_timing(bcts_ctx* ctx, double* out24);

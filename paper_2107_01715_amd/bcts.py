@@ -39,7 +39,9 @@ EXPORTS = (
     "bcts_search", "bcts_search_batch", "bcts_search_batch_device", "bcts_search_batch_graph",
     "bcts_submit", "bcts_progress", "bcts_poll", "bcts_serve_config", "bcts_request_bytes",
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
+    "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
 )
+TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK = 0, 1, 2, 3
 
 
 class EnvParamsC(ctypes.Structure):
@@ -89,6 +91,10 @@ _debug_expand = _sig("bcts_debug_expand", c_int32, _P, _P, _P, c_int32, c_int32,
 _debug_qnet = _sig("bcts_debug_qnet", c_int32, _P, c_int32, _P, c_int32, _P)
 _set_timing = _sig("bcts_set_timing", c_int32, _P, c_int32)
 _get_timing = _sig("bcts_get_timing", c_int32, _P, _P)
+_set_tuning = _sig("bcts_set_tuning", c_int32, _P, c_int32, ctypes.c_int64)
+_get_tuning = _sig("bcts_get_tuning", c_int32, _P, c_int32, POINTER(ctypes.c_int64))
+_autotune = _sig("bcts_autotune", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, CorrectionC, _P, _P, c_int32, _P,
+                 POINTER(ctypes.c_int64))
 
 
 def _ptr(a: np.ndarray):
@@ -280,6 +286,27 @@ def bcts_get_timing(ctx) -> np.ndarray:
     out = np.zeros(24, np.float64)
     _check(ctx, _get_timing(ctx, _ptr(out)))
     return out
+
+
+def bcts_set_tuning(ctx, key: int, value: int):
+    _check(ctx, _set_tuning(ctx, key, int(value)))
+
+
+def bcts_get_tuning(ctx, key: int) -> int:
+    v = ctypes.c_int64()
+    _check(ctx, _get_tuning(ctx, key, byref(v)))
+    return v.value
+
+
+def bcts_autotune(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, reps=2, stream=None):
+    """Returns {fused, round, chunk, us_per_search} and keeps it on ctx."""
+    d = _arr(depth, np.int32)
+    a = _arr(A, np.int32)
+    s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = (ctypes.c_int64 * 4)()
+    _check(ctx, _autotune(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8), _ptr(d),
+                          _ptr(a), gamma, corr, _dev(act_t, torch.int32), _dev(q_t, torch.float32), reps, s, out))
+    return {"fused": int(out[0]), "round": int(out[1]), "chunk": int(out[2]), "us_per_search": int(out[3])}
 
 
 # ---- convenience object ----------------------------------------------------

@@ -65,6 +65,12 @@ void gev_coeffs(int A, int d, double* pe, double* po) {
   *po = gev_bias(no) / std::sqrt(2.0);
 }
 
+// fused path: x3 [chunk][3136] and h [chunk][512] in the operand type
+size_t fused_workspace_bytes(long long chunk, int prec) {
+  const size_t el = prec == P_BF16 ? 2 : 1;
+  return (size_t)chunk * 3136 * el + 256 + (size_t)chunk * 512 * el + 256;
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -80,7 +86,12 @@ struct Plan {
   long long lvl_count[kMaxD + 1] = {0};
   std::vector<int> lvl_root[kMaxD + 1];
   std::vector<long long> lvl_start[kMaxD + 1];
-  long long chunk = 0;
+  long long chunk = 0;                 // max items of a chunk
+  bool fused = false;                  // conv stack fused per sibling group
+  std::vector<FusedGroup> groups;      // sibling groups in item order
+  struct Chunk { int g0, g1; long long i0, i1; };
+  std::vector<Chunk> chunks;           // whole groups, ~chunk_items items each
+  size_t o_groups = 0;
   // arena offsets
   size_t o_root_pos = 0, o_root_stack = 0, o_roots = 0, o_segs = 0, o_V = 0, o_q0 = 0,
          o_desc = 0, o_ws = 0, o_act = 0, o_q = 0, total = 0;
@@ -98,7 +109,10 @@ struct bcts_ctx {
   bool env_set = false, qnet_set = false;
   EnvTables env{};
   int prec = P_FP32;
-  long long chunk_items = 8192;
+  long long chunk_items = 8192;        // layer-by-layer path (FP32)
+  long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
+  int fused_T = 3;                      // items per LDS round of the fused conv kernel
+  bool fused = true;
   // weights
   void* wmem = nullptr;
   size_t wbytes = 0;
@@ -116,6 +130,7 @@ struct bcts_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> tev;      // [start, level 1..maxd, chunk x 6, qnet end, end]
   int t_maxd = 0, t_chunks = 0;
+  bool t_fused = false;
   long long t_items = 0, t_nodes = 0;
   double t_ms[24] = {0};
   // serving
@@ -216,8 +231,9 @@ bcts_status validate_pos(bcts_ctx* c, int n, const int32_t* pos) {
 // single root-kind eval (debug Q-network on stacks).
 void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
                const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
-               bool host_io) {
+               bool host_io, bool fused = false) {
   p = Plan();
+  p.fused = fused && prec != P_FP32;
   p.n = n;
   p.roots.resize(n);
   for (int r = 0; r < n; ++r) p.maxd = std::max(p.maxd, (int)depth[r]);
@@ -274,14 +290,41 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     }
   }
   p.n_items = item;
-  p.chunk = std::min(item, chunk_items);
-  if (p.chunk < 1) p.chunk = 1;
+  // sibling groups: the A children of each level-(d-1) node, the A depth-1
+  // nodes of a root, a root alone; chunks hold whole groups
+  for (const Seg& sg : p.segs) {
+    const RootInfo& ri = p.roots[sg.root];
+    long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : 1);
+    if (sg.kind == 0) for (int k = 0; k < ri.d; ++k) cnt *= ri.A;
+    const int gsz = sg.kind == 2 ? 1 : ri.A;
+    for (long long j = 0; j < cnt; j += gsz) p.groups.push_back(FusedGroup{sg.item0 + j, gsz, 0});
+  }
+  {
+    const long long target = std::max(1LL, chunk_items);
+    int g = 0;
+    p.chunk = 1;
+    while (g < (int)p.groups.size()) {
+      Plan::Chunk ch;
+      ch.g0 = g;
+      ch.i0 = p.groups[g].item0;
+      long long items = 0;
+      while (g < (int)p.groups.size() && (items == 0 || items + p.groups[g].count <= target)) {
+        items += p.groups[g].count;
+        ++g;
+      }
+      ch.g1 = g;
+      ch.i1 = ch.i0 + items;
+      p.chunk = std::max(p.chunk, items);
+      p.chunks.push_back(ch);
+    }
+  }
 
   // arena layout
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
   p.o_roots = take(sizeof(RootInfo) * n);
   p.o_segs = take(sizeof(Seg) * p.segs.size());
+  p.o_groups = take(sizeof(FusedGroup) * p.groups.size());
   for (int k = 1; k <= p.maxd; ++k) {
     p.o_lroot[k] = take(sizeof(int) * p.lvl_root[k].size());
     p.o_lstart[k] = take(sizeof(long long) * p.lvl_start[k].size());
@@ -302,8 +345,15 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
   p.o_V = take(sizeof(float) * p.n_items);
   p.o_q0 = take(sizeof(float) * (size_t)n * kMaxA);
   p.o_desc = take(sizeof(ItemDesc) * p.chunk);
-  p.o_ws = take(qnet_workspace_bytes(p.chunk, prec));
+  p.o_ws = take(p.fused ? fused_workspace_bytes(p.chunk, prec) : qnet_workspace_bytes(p.chunk, prec));
   p.total = o;
+}
+
+// Plan a search with the context's Q-network path settings.
+void plan_search(bcts_ctx* c, Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
+                 const bcts_correction& corr, int q_stride, bool host_io) {
+  const bool fz = c->fused && c->prec != P_FP32;
+  make_plan(p, n, depth, A, gamma, corr, q_stride, fz ? c->fused_chunk_items : c->chunk_items, c->prec, host_io, fz);
 }
 
 // Copy the plan's tables to `arena` through the pinned staging buffer `h`
@@ -311,6 +361,7 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
 bcts_status upload_tables_at(bcts_ctx* c, const Plan& p, char* arena, char* h, hipStream_t s) {
   std::memcpy(h + p.o_roots, p.roots.data(), sizeof(RootInfo) * p.n);
   std::memcpy(h + p.o_segs, p.segs.data(), sizeof(Seg) * p.segs.size());
+  std::memcpy(h + p.o_groups, p.groups.data(), sizeof(FusedGroup) * p.groups.size());
   for (int k = 1; k <= p.maxd; ++k) {
     std::memcpy(h + p.o_lroot[k], p.lvl_root[k].data(), sizeof(int) * p.lvl_root[k].size());
     std::memcpy(h + p.o_lstart[k], p.lvl_start[k].data(), sizeof(long long) * p.lvl_start[k].size());
@@ -337,11 +388,61 @@ bcts_status ensure_events(bcts_ctx* c, size_t n) {
   return BCTS_OK;
 }
 
+// Q-network over every eval item of the plan, chunk by chunk.  With `ev`
+// (6 events per chunk) the launches of each chunk are bracketed.
+bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameBases& fb, hipStream_t s,
+                               hipEvent_t* ev) {
+  const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
+  ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
+  float* V = reinterpret_cast<float*>(A + p.o_V);
+  float* q0 = reinterpret_cast<float*>(A + p.o_q0);
+  const int nchunks = (int)p.chunks.size();
+  const FusedGroup* groups = reinterpret_cast<const FusedGroup*>(A + p.o_groups);
+  for (int ci = 0; ci < nchunks; ++ci) {
+    const Plan::Chunk& ch = p.chunks[ci];
+    const long long cnt = ch.i1 - ch.i0;
+    hipEvent_t* cev = ev ? ev + 6 * ci : nullptr;
+    launch_item_desc(ch.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
+    if (!p.fused) {
+      launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + ch.i0, q0, s, cev);
+      continue;
+    }
+    const QnetDev& q = c->q;
+    FusedConvArgs fa{};
+    fa.groups = groups + ch.g0;
+    fa.item_base = ch.i0;
+    fa.desc = desc;
+    const bool f8 = c->prec == P_FP8;
+    for (int l = 0; l < 3; ++l) {
+      fa.w[l] = f8 ? (const void*)q.w8[l] : (const void*)q.wb[l];
+      fa.bias[l] = q.b[l];
+      fa.acc_scale[l] = f8 ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
+      fa.out_s8[l] = f8 ? q.ascale[l + 1] : 1.f;
+    }
+    fa.acc_scale[0] /= 255.f;
+    fa.pix_s8 = f8 ? q.ascale[0] : 1.f;
+    const size_t el = f8 ? 1 : 2;
+    char* x3 = A + p.o_ws;
+    char* h = x3 + align_up((size_t)p.chunk * 3136 * el);
+    fa.x3 = x3;
+    if (cev) HIPCHECK(c, hipEventRecord(cev[0], s));
+    launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s);
+    if (cev) {
+      HIPCHECK(c, hipEventRecord(cev[1], s));
+      HIPCHECK(c, hipEventRecord(cev[2], s));
+      HIPCHECK(c, hipEventRecord(cev[3], s));
+    }
+    launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr);
+    if (cev) HIPCHECK(c, hipEventRecord(cev[5], s));
+  }
+  return BCTS_OK;
+}
+
 bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t* d_pos,
                               const uint8_t* d_stacks, float gamma, float corr_scale, int32_t* d_act,
                               float* d_q, hipStream_t s, bool timed) {
   const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
-  const int nchunks = (int)((p.n_items + p.chunk - 1) / p.chunk);
+  const int nchunks = (int)p.chunks.size();
   hipEvent_t* ev = nullptr;
   if (timed) {
     bcts_status st = ensure_events(c, (size_t)(3 + p.maxd + 6 * nchunks));
@@ -349,6 +450,7 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
     ev = c->tev.data();
     c->t_maxd = p.maxd;
     c->t_chunks = nchunks;
+    c->t_fused = p.fused;
     c->t_items = p.n_items;
     c->t_nodes = 0;
     for (int k = 1; k <= p.maxd; ++k) c->t_nodes += p.lvl_count[k];
@@ -369,14 +471,11 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
   FrameBases fb{};
   fb.level_frames[0] = d_stacks;
   for (int k = 1; k <= p.maxd; ++k) fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
-  ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
   float* V = reinterpret_cast<float*>(A + p.o_V);
   float* q0 = reinterpret_cast<float*>(A + p.o_q0);
-  int ci = 0;
-  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk, ++ci) {
-    const long long cnt = std::min(p.chunk, p.n_items - i0);
-    launch_item_desc(i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
-    launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + i0, q0, s, timed ? ev + 1 + p.maxd + 6 * ci : nullptr);
+  {
+    bcts_status st = enqueue_qnet_stage(c, p, A, fb, s, timed ? ev + 1 + p.maxd : nullptr);
+    if (st != BCTS_OK) return st;
   }
   if (timed) HIPCHECK(c, hipEventRecord(ev[1 + p.maxd + 6 * nchunks], s));
   LevelRet lr{};
@@ -418,6 +517,7 @@ bcts_status collect_timing(bcts_ctx* c) {
   for (int k = 1; k <= D; ++k) c->t_ms[9 + k] = el(k - 1, k);
   c->t_ms[16] = (double)c->t_items;
   c->t_ms[17] = (double)c->t_nodes;
+  c->t_ms[18] = c->t_fused ? 1.0 : 0.0;
   return BCTS_OK;
 }
 
@@ -426,7 +526,7 @@ bcts_status search_host(bcts_ctx* c, int n, const int32_t* pos, const uint8_t* s
                         const int32_t* Av, float gamma, const bcts_correction& corr, int32_t* out_action,
                         float* out_q, int q_stride) {
   Plan p;
-  make_plan(p, n, depth, Av, gamma, corr, q_stride, c->chunk_items, c->prec, true);
+  plan_search(c, p, n, depth, Av, gamma, corr, q_stride, true);
   bcts_status st = ensure_arena(c, p.total);
   if (st != BCTS_OK) return st;
   hipStream_t s = c->stream;
@@ -526,8 +626,12 @@ struct ServeEngine {
   explicit ServeEngine(bcts_ctx* ctx) : c(ctx) {}
   ~ServeEngine() { release(); }
 
+  long long chunk_items() const { return (c->fused && c->prec != P_FP32) ? 8 * chunk : chunk; }
   size_t fixed_bytes() const {
-    return qnet_workspace_bytes(chunk, c->prec) + sizeof(ItemDesc) * chunk + 8 * kAlign;
+    const long long ch = chunk_items() + kMaxA;
+    const size_t ws = (c->fused && c->prec != P_FP32) ? fused_workspace_bytes(ch, c->prec)
+                                                       : qnet_workspace_bytes(ch, c->prec);
+    return ws + sizeof(ItemDesc) * ch + 8 * kAlign;
   }
 
   void release() {
@@ -602,10 +706,11 @@ struct ServeEngine {
     std::vector<int32_t> dep(n), Av(n);
     for (int i = 0; i < n; ++i) { dep[i] = queue[i].d; Av[i] = queue[i].A; }
     Plan p;
-    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk, c->prec, true);
+    const bool fz = c->fused && c->prec != P_FP32;
+    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz);
     while (p.total > slot_cap && n > 1) {   // alignment slack: shrink the batch
       --n;
-      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk, c->prec, true);
+      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz);
     }
     if (p.total > slot_cap) return fail(c, BCTS_E_NOMEM, "request does not fit a serving slot");
     if (sl.arena_bytes < slot_cap) {
@@ -941,7 +1046,7 @@ bcts_status bcts_search_batch_device(bcts_ctx* c, int32_t n, const int32_t* d_po
   HIPCHECK(c, hipSetDevice(c->device));
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
   Plan p;
-  make_plan(p, n, depth, A, gamma, corr, kMaxA, c->chunk_items, c->prec, false);
+  plan_search(c, p, n, depth, A, gamma, corr, kMaxA, false);
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
   st = enqueue_search(c, p, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, s, c->timing);
@@ -963,7 +1068,7 @@ bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos
   HIPCHECK(c, hipSetDevice(c->device));
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
   Plan p;
-  make_plan(p, n, depth, A, gamma, corr, kMaxA, c->chunk_items, c->prec, false);
+  plan_search(c, p, n, depth, A, gamma, corr, kMaxA, false);
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
   HIPCHECK(c, hipStreamSynchronize(s));
@@ -1056,7 +1161,7 @@ bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32
   std::vector<int32_t> dep(n, 0), Av(n, A);
   bcts_correction off{0, 0.f, 0};
   Plan p;
-  make_plan(p, n, dep.data(), Av.data(), 1.f, off, kMaxA, c->chunk_items, c->prec, true);
+  plan_search(c, p, n, dep.data(), Av.data(), 1.f, off, kMaxA, true);
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   hipStream_t s = c->stream;
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
@@ -1064,15 +1169,8 @@ bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32
                              hipMemcpyHostToDevice, s));
   FrameBases fb{};
   fb.level_frames[0] = reinterpret_cast<const uint8_t*>(c->arena + p.o_root_stack);
-  ItemDesc* desc = reinterpret_cast<ItemDesc*>(c->arena + p.o_desc);
   float* q0 = reinterpret_cast<float*>(c->arena + p.o_q0);
-  for (long long i0 = 0; i0 < p.n_items; i0 += p.chunk) {
-    const long long cnt = std::min(p.chunk, p.n_items - i0);
-    launch_item_desc(i0, cnt, reinterpret_cast<const Seg*>(c->arena + p.o_segs), (int)p.segs.size(),
-                     reinterpret_cast<const RootInfo*>(c->arena + p.o_roots), fb, desc, s);
-    launch_qnet(c->prec, c->q, desc, cnt, c->arena + p.o_ws, reinterpret_cast<float*>(c->arena + p.o_V) + i0,
-                q0, s);
-  }
+  if ((st = enqueue_qnet_stage(c, p, c->arena, fb, s, nullptr)) != BCTS_OK) return st;
   HIPCHECK(c, hipGetLastError());
   std::vector<float> h((size_t)n * kMaxA);
   HIPCHECK(c, hipMemcpyAsync(h.data(), q0, h.size() * 4, hipMemcpyDeviceToHost, s));
@@ -1157,6 +1255,114 @@ bcts_status bcts_poll(bcts_ctx* c, uint64_t ticket, int32_t* action, float* q, d
   if (t_done) *t_done = it->second.t_done;
   c->serve->results.erase(it);
   c->serve->live.erase(ticket);
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  switch (key) {
+    case BCTS_TUNE_FUSED:
+      c->fused = value != 0;
+      return BCTS_OK;
+    case BCTS_TUNE_FUSED_ROUND:
+      if (value < 1 || value > 4) return fail(c, BCTS_E_INVAL, "fused round must be 1..4");
+      c->fused_T = (int)value;
+      return BCTS_OK;
+    case BCTS_TUNE_FUSED_CHUNK:
+      if (value < 1 || value > (1LL << 26)) return fail(c, BCTS_E_INVAL, "fused chunk out of range");
+      c->fused_chunk_items = value;
+      return BCTS_OK;
+    case BCTS_TUNE_LAYER_CHUNK:
+      if (value < 1 || value > (1LL << 22)) return fail(c, BCTS_E_INVAL, "layer chunk out of range");
+      c->chunk_items = value;
+      return BCTS_OK;
+    default:
+      return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
+  }
+}
+
+bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
+  if (!c || !value) return BCTS_E_INVAL;
+  switch (key) {
+    case BCTS_TUNE_FUSED: *value = c->fused ? 1 : 0; return BCTS_OK;
+    case BCTS_TUNE_FUSED_ROUND: *value = c->fused_T; return BCTS_OK;
+    case BCTS_TUNE_FUSED_CHUNK: *value = c->fused_chunk_items; return BCTS_OK;
+    case BCTS_TUNE_LAYER_CHUNK: *value = c->chunk_items; return BCTS_OK;
+    default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
+  }
+}
+
+bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
+                          const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                          void* d_scratch_action, void* d_scratch_q, int32_t reps, void* hip_stream,
+                          int64_t* out_best) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (reps < 1 || !out_best) return fail(c, BCTS_E_INVAL, "reps >= 1 and out_best required");
+  // candidates: fused on/off (FP32 is never fused), round T, fused chunk size
+  const int Ts[4] = {1, 2, 3, 4};
+  const long long chunks[2] = {262144, 1048576};
+  const bool was_fused = c->fused, was_timing = c->timing;
+  const int was_T = c->fused_T;
+  const long long was_chunk = c->fused_chunk_items;
+  double best_ms = 1e30;
+  int64_t best[4] = {was_fused, was_T, was_chunk, 0};
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  c->timing = false;
+  for (int fz = (c->prec == P_FP32 ? 0 : 1); fz >= 0 && st == BCTS_OK; --fz) {
+    for (int ti = 0; ti < (fz ? 4 : 1) && st == BCTS_OK; ++ti) {
+      if (fz && c->prec == P_BF16 && Ts[ti] == 4) continue;   // over the LDS of one CU
+      for (int ci = 0; ci < (fz ? 2 : 1) && st == BCTS_OK; ++ci) {
+        c->fused = fz != 0;
+        c->fused_T = Ts[ti];
+        c->fused_chunk_items = chunks[ci];
+        st = bcts_search_batch_device(c, n, d_pos, d_stacks, depth, A, gamma, corr,
+                                      reinterpret_cast<int32_t*>(d_scratch_action),
+                                      reinterpret_cast<float*>(d_scratch_q), s);   // warm-up, allocation
+        if (st == BCTS_E_NOMEM) { st = BCTS_OK; c->err.clear(); continue; }
+        if (st != BCTS_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(c, BCTS_E_HIP, "event record failed"); break; }
+        for (int r = 0; r < reps && st == BCTS_OK; ++r)
+          st = bcts_search_batch_device(c, n, d_pos, d_stacks, depth, A, gamma, corr,
+                                        reinterpret_cast<int32_t*>(d_scratch_action),
+                                        reinterpret_cast<float*>(d_scratch_q), s);
+        if (st != BCTS_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(c, BCTS_E_HIP, "event timing failed");
+          break;
+        }
+        ms /= reps;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[0] = fz;
+          best[1] = Ts[ti];
+          best[2] = chunks[ci];
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->timing = was_timing;
+  if (st != BCTS_OK) {
+    c->fused = was_fused;
+    c->fused_T = was_T;
+    c->fused_chunk_items = was_chunk;
+    return st;
+  }
+  c->fused = best[0] != 0;
+  c->fused_T = (int)best[1];
+  c->fused_chunk_items = best[2];
+  out_best[0] = best[0];
+  out_best[1] = best[1];
+  out_best[2] = best[2];
+  out_best[3] = (int64_t)(best_ms * 1000.0);   // microseconds per search
   return BCTS_OK;
 }
 

@@ -74,6 +74,28 @@ struct FrameBases {
   const uint8_t* level_frames[kMaxD + 1];
 };
 
+// A sibling group: consecutive eval items whose stacks share channels 0..2
+// (the A children of one node, the A depth-1 nodes of a root, or one root).
+struct FusedGroup {
+  long long item0;             // first item (plan-global index)
+  int count;
+  int pad_;
+};
+
+// Arguments of the fused conv1->conv2->conv3 kernel (BF16 / FP8).
+struct FusedConvArgs {
+  const FusedGroup* groups;    // groups of this chunk
+  long long item_base;         // plan-global index of desc[0]
+  const ItemDesc* desc;        // chunk-relative item descriptors
+  const void* w[3];            // conv weights in operand type, GEMM layout [N][K]
+  const float* bias[3];
+  float acc_scale[3];          // accumulator scale (1/255 on conv1; fp8 operand scales)
+  float out_s8[3];             // fp8: input scale of the next layer
+  float pix_s8;                // fp8: pixel scale
+  void* x3;                    // out: [chunk items][49][64] channels-last
+};
+void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s);
+
 // Precisions (mirrors bcts_precision).
 enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
 
@@ -87,6 +109,12 @@ struct QnetDev {
   float wscale[5];             // fp8 weight scale: w8 = e4m3(w * wscale)
   float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
 };
+
+// fc1 (+ReLU) and fc2 (+max over A, root rows of Q_0) over a chunk whose
+// conv3 output x3 is ready; `h` holds [n][512] in the operand type.
+void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
+                    const void* x3, void* h, float* V, float* q0, hipStream_t s,
+                    hipEvent_t ev_after_fc1 = nullptr);
 
 // ---- launchers (each in the TU that defines its kernels) ----------------
 void launch_expand(int k, long long n_nodes, LevelRoots lr, const RootInfo* roots,

@@ -470,6 +470,23 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, flo
   if (ev) (void)hipEventRecord(ev[5], s);
 }
 
+template <int P>
+void run_fc(const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h, float* V, float* q0,
+            hipStream_t s, hipEvent_t ev) {
+  auto wp = [&](int l) -> const void* {
+    return P == P_FP32 ? (const void*)q.w[l] : P == P_BF16 ? (const void*)q.wb[l] : (const void*)q.w8[l];
+  };
+  auto accs = [&](int l) { return (P == P_FP8) ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f; };
+  LayerArgs a{};
+  a.desc = desc;
+  a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3);
+  a.out_s8 = P == P_FP8 ? q.ascale[4] : 1.f; a.out = h;
+  run_layer<3, P>(a, s);
+  if (ev) (void)hipEventRecord(ev, s);
+  a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
+  run_layer<4, P>(a, s);
+}
+
 __global__ void to_bf16_kernel(const float* __restrict__ s, uint16_t* __restrict__ d, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = f2bf(s[i]);
@@ -507,6 +524,14 @@ void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n, 
   if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, ws, V, q0, s, ev);
   else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, ws, V, q0, s, ev);
   else run_qnet<P_FP8>(q, desc, n, ws, V, q0, s, ev);
+}
+
+void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h,
+                    float* V, float* q0, hipStream_t s, hipEvent_t ev) {
+  if (n <= 0) return;
+  if (prec == P_FP32) run_fc<P_FP32>(q, desc, n, x3, h, V, q0, s, ev);
+  else if (prec == P_BF16) run_fc<P_BF16>(q, desc, n, x3, h, V, q0, s, ev);
+  else run_fc<P_FP8>(q, desc, n, x3, h, V, q0, s, ev);
 }
 
 void launch_convert_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) {

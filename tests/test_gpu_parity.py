@@ -235,3 +235,52 @@ def test_state_errors(lib):
         ctx.search(pos, st, 1, 4, GAMMA, lib.correction(True, 1.0))
     assert e.value.status == lib.E_STATE
     ctx.close()
+
+
+def test_fused_matches_layer_path(lib, setup):
+    """The fused conv kernel (conv1's shared channels summed once per sibling
+    group) against the layer-by-layer kernels at the same operand precision:
+    only FP32 summation order and the occasional BF16 rounding flip differ."""
+    ctx, world, _ = setup
+    pos, st = W.roots(41, 12)
+    A, d = 6, 2
+    corr = lib.correction(True, 1.0)
+    ctx.set_precision(lib.BF16)
+    ctx.set_tuning(lib.TUNE_FUSED, 0)
+    a0, q0 = ctx.search(pos, st, d, A, GAMMA, corr)
+    ctx.set_tuning(lib.TUNE_FUSED, 1)
+    a1, q1 = ctx.search(pos, st, d, A, GAMMA, corr)
+    ctx.set_precision(lib.FP32)
+    rel = np.abs(q1 - q0).max(axis=1) / np.abs(q0).max(axis=1)
+    assert rel.max() < 5e-3, rel.max()
+    assert (a0 == a1).mean() >= 11 / 12
+
+
+@pytest.mark.parametrize("prec_name,rounds", [("BF16", (1, 2, 3)), ("FP8", (1, 2, 3, 4))])
+def test_fused_rounds_and_chunks_are_bitwise_identical(lib, setup, prec_name, rounds):
+    """Round size and chunking change only how stacks are grouped into
+    launches and LDS rounds, never a stack's arithmetic."""
+    ctx, _, _ = setup
+    n = 20
+    pos, st = W.roots(1004, n)
+    A, d = W.mixed_shapes(1004, n, (4, 6, 18), (0, 1, 2, 3))
+    d = np.where(A == 18, np.minimum(d, 2), d)
+    corr = lib.correction(True, 1.0)
+    if prec_name == "FP8":
+        _, cal = W.roots(2003, 64)
+        ctx.calibrate_fp8(cal)
+    ctx.set_precision(getattr(lib, prec_name))
+    ref = None
+    for T in rounds:
+        for chunk in (37, 262144):
+            ctx.set_tuning(lib.TUNE_FUSED_ROUND, T)
+            ctx.set_tuning(lib.TUNE_FUSED_CHUNK, chunk)
+            act, q = ctx.search_batch(pos, st, d, A, GAMMA, corr)
+            if ref is None:
+                ref = (act, q)
+            else:
+                assert np.array_equal(act, ref[0]), (T, chunk)
+                assert np.array_equal(q, ref[1]), (T, chunk)
+    ctx.set_tuning(lib.TUNE_FUSED_ROUND, 3)
+    ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 262144)
+    ctx.set_precision(lib.FP32)
