@@ -31,6 +31,12 @@ constexpr int kThreads = 256;
 constexpr int kBM = 128;       // rows per workgroup tile
 constexpr int kBKU = 4;        // K units (of 8) per LDS stage: 32 K values
 
+// Barrier for LDS hand-offs only: unlike __syncthreads() it does not wait for
+// outstanding global loads, so the next stage's prefetch stays in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---- element types ------------------------------------------------------
 template <int P> struct PT;
 template <> struct PT<P_FP32> { typedef float T; };
@@ -335,14 +341,14 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
 
   gload(0);
   lstore();
-  __syncthreads();
+  lds_barrier();
   for (int st = 0; st < NSTAGE; ++st) {
     if (st + 1 < NSTAGE) gload(st + 1);
     mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
-    __syncthreads();
+    lds_barrier();
     if (st + 1 < NSTAGE) {
       lstore();
-      __syncthreads();
+      lds_barrier();
     }
   }
 
@@ -377,7 +383,7 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
         for (int q = 0; q < 4; ++q)
           Cs[(wave * 32 + i * 16 + rq + q) * 33 + n] = acc[i][j][q] * args.acc_scale + b;
       }
-    __syncthreads();
+    lds_barrier();
     if (tid < kBM) {
       const long long m = m0 + tid;
       if (m < args.M) {

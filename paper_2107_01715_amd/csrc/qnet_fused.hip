@@ -11,7 +11,7 @@
 // S is computed once per group and kept in registers; each item then adds
 // only its own channel (a quarter of conv1's K).
 //
-// Data path of a workgroup (4 wavefronts):
+// Data path of a workgroup (8 wavefronts):
 //   * a frame is read from HBM once, converted to the operand type once and
 //     staged in LDS (double-buffered; the next item's frame is loaded into
 //     registers while the current one is used);
@@ -24,7 +24,7 @@
 // accumulate): the weights are the A operand and the im2col pixels the B
 // operand, so each lane ends with 4 consecutive channels of one pixel and
 // stores them with one 8-byte (BF16) or 4-byte (FP8) write.  A wavefront owns
-// a set of 16-pixel fragments and all channel fragments of a layer.  The sum
+// a set of 16-pixel fragments and half the channel fragments of a layer.  The sum
 // order of every output element is fixed by the layer, never by the group
 // size, round size or chunking, so results do not depend on batching.
 #include "bcts_internal.h"
@@ -37,9 +37,8 @@ typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
-constexpr int kThreads = 256;
-constexpr int kWaves = 4;
-constexpr int kF1 = 7;                 // conv1 pixel fragments per wave: w, w+4, ... < 25
+constexpr int kThreads = 512;          // 8 wavefronts
+constexpr int kF1 = 7;                 // conv1 pixel fragments per wave: (w>>1) + 4i
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -53,6 +52,19 @@ __device__ __forceinline__ unsigned fp8_pack4(float a, float b, float c, float d
   const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
   return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
 }
+
+// Workgroup barrier for LDS hand-offs only.  __syncthreads() also waits for
+// every outstanding global load (its workgroup fence drains vmcnt), which
+// would cancel the frame and weight prefetches at each barrier; here only
+// the LDS queue is drained before s_barrier, global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Keep global prefetch loads where they are issued: the scheduler may move
+// ALU, MFMA and LDS instructions across this point, but no global read, so a
+// prefetch is not sunk next to its first use.
+__device__ __forceinline__ void pin_vmem_reads() { __builtin_amdgcn_sched_barrier(0x78F); }
 
 // ---- operand traits ------------------------------------------------------
 // EB: bytes per element; UB: bytes per 8-element unit (one lane's K group).
@@ -116,30 +128,46 @@ template <> struct F<P_FP8> {
   }
 };
 
-// Swizzled LDS layouts (byte offsets).  x1: per item 400 pixels x 32
-// channels; two pixels form a row of 8 units and unit ((p&1)*4 + c/8) is
-// stored at slot ^ ((p>>1) & 7).  x2: per item 81 pixels x 64 channels; one
-// pixel is a row of 8 units, unit c/8 at slot ^ (p & 7).
-template <int P> __device__ __forceinline__ int x1_off(int t, int p, int c) {
-  constexpr int UB = F<P>::UB, EB = F<P>::EB;
-  return t * 400 * 32 * EB + (p >> 1) * 8 * UB + (((((p & 1) << 2) | (c >> 3)) ^ ((p >> 1) & 7)) * UB) +
-         (c & 7) * EB;
-}
-template <int P> __device__ __forceinline__ int x2_off(int t, int p, int c) {
-  constexpr int UB = F<P>::UB, EB = F<P>::EB;
-  return t * 81 * 64 * EB + p * 8 * UB + (((c >> 3) ^ (p & 7)) * UB) + (c & 7) * EB;
-}
+// LDS layouts (byte offsets), padded so that the MFMA operand reads of 8
+// consecutive lanes (b128, BF16) or 16 lanes (b64, FP8) hit distinct banks,
+// and arranged so that every K step of a lane reads at a compile-time offset
+// from one per-fragment base address.
+//  x1: conv1 output 20x20x32 split into the 4 stride-2 phases (y&1, x&1) of
+//      10x10 pixels each; pixel stride 40 elements (32 channels + 8 pad).
+//      conv2's input pixel (2oy+kh, 2ox+kw) is then pixel (oy + kh/2,
+//      ox + kw/2) of phase (kh&1, kw&1): neighbouring output pixels read
+//      neighbouring LDS pixels.
+//  x2: conv2 output 9x9x64, pixel stride 72 elements (64 channels + 8 pad).
+template <int P> struct Lay {
+  static constexpr int EB = F<P>::EB;
+  static constexpr int X1P = 40 * EB;               // pixel stride
+  static constexpr int X1PH = 100 * X1P;            // phase stride
+  static constexpr int X1T = 4 * X1PH;              // item stride
+  static constexpr int X2P = 72 * EB;
+  static constexpr int X2T = 81 * X2P;
+  __device__ static int x1(int t, int y, int x, int c) {
+    return t * X1T + ((y & 1) * 2 + (x & 1)) * X1PH + ((y >> 1) * 10 + (x >> 1)) * X1P + c * EB;
+  }
+  __device__ static int x2(int t, int p, int c) { return t * X2T + p * X2P + c * EB; }
+};
 
+// One workgroup of 8 wavefronts per CU (the rounds use most of the LDS), so
+// two wavefronts share each SIMD and cover each other's memory latency.
+// Wavefronts work in pairs: wave w takes channel half (w & 1) of every layer
+// and pixel fragments (w >> 1) + 4i.  conv2/conv3 weight fragments stream
+// from L2 two K steps ahead.
 template <int P, int T>
-__global__ void __launch_bounds__(kThreads, (T <= 2 ? 2 : 1)) conv_fused_kernel(FusedConvArgs a) {
+__global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
+  constexpr int RS = 3;     // weight ring: RS-1 K steps ahead
   typedef F<P> Fr;
   typedef typename Fr::V V;
   constexpr int EB = Fr::EB;
   constexpr int FRB = kFrameBytes * EB;                 // staged frame bytes
-  constexpr int R2 = T * 81, F2 = (R2 + 15) / 16, F2W = (F2 + kWaves - 1) / kWaves;
-  constexpr int R3 = T * 49, F3 = (R3 + 15) / 16, F3W = (F3 + kWaves - 1) / kWaves;
-  __shared__ __attribute__((aligned(16))) unsigned char x1[T * 400 * 32 * EB];
-  __shared__ __attribute__((aligned(16))) unsigned char x2[T * 81 * 64 * EB];
+  constexpr int R2 = T * 81, F2 = (R2 + 15) / 16, F2W = (F2 + 3) / 4;
+  constexpr int R3 = T * 49, F3 = (R3 + 15) / 16, F3W = (F3 + 3) / 4;
+  typedef Lay<P> L;
+  __shared__ __attribute__((aligned(16))) unsigned char x1[T * L::X1T];
+  __shared__ __attribute__((aligned(16))) unsigned char x2[T * L::X2T];
   __shared__ __attribute__((aligned(16))) unsigned char fs[2][FRB];
 
   const FusedGroup grp = a.groups[blockIdx.x];
@@ -147,83 +175,74 @@ __global__ void __launch_bounds__(kThreads, (T <= 2 ? 2 : 1)) conv_fused_kernel(
   const long long i0 = grp.item0 - a.item_base;   // chunk-relative first item
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
+  const int half = wave & 1, fq = wave >> 1;      // channel half, first pixel fragment
   const unsigned char* W1 = reinterpret_cast<const unsigned char*>(a.w[0]);
   const unsigned char* W2 = reinterpret_cast<const unsigned char*>(a.w[1]);
   const unsigned char* W3 = reinterpret_cast<const unsigned char*>(a.w[2]);
   unsigned char* X3 = reinterpret_cast<unsigned char*>(a.x3);
   const float s8 = a.pix_s8;
 
-  // frame staging: 441 16-byte chunks; thread t takes chunks t and t + 256
-  const bool c2 = tid + kThreads < kFrameBytes / 16;
-  auto fload = [&](const uint8_t* fr, uint4& u0, uint4& u1) {
-    u0 = reinterpret_cast<const uint4*>(fr)[tid];
-    if (c2) u1 = reinterpret_cast<const uint4*>(fr)[tid + kThreads];
+  // frame staging: 441 16-byte chunks, one per thread
+  const bool cf = tid < kFrameBytes / 16;
+  auto fload = [&](const uint8_t* fr, uint4& u) {
+    if (cf) u = reinterpret_cast<const uint4*>(fr)[tid];
   };
-  auto fstore = [&](int buf, const uint4& u0, const uint4& u1) {
-    Fr::stage16(&fs[buf][tid * 16 * EB], u0, s8);
-    if (c2) Fr::stage16(&fs[buf][(tid + kThreads) * 16 * EB], u1, s8);
+  auto fstore = [&](int buf, const uint4& u) {
+    if (cf) Fr::stage16(&fs[buf][tid * 16 * EB], u, s8);
   };
 
-  // conv1 weights (A operand): K step s covers stack channel s/2, kernel rows
-  // 4(s&1)..+3; lane group g holds kernel row 4(s&1)+g (8 kw values)
-  V w1[8][2];
+  // conv1 weights (A operand) of this wave's channel half: K step s covers
+  // stack channel s/2, kernel rows 4(s&1)..+3; lane group g holds kernel row
+  // 4(s&1)+g (8 kw values)
+  V w1[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
+  for (int s = 0; s < 8; ++s) w1[s] = Fr::ld(W1 + ((16 * half + r16) * 256 + 32 * s + 8 * g) * EB);
+  float b1[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) w1[s][j] = Fr::ld(W1 + ((16 * j + r16) * 256 + 32 * s + 8 * g) * EB);
-  float b1[2][4];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b1[j][q] = a.bias[0][16 * j + 4 * g + q];
+  for (int q = 0; q < 4; ++q) b1[q] = a.bias[0][16 * half + 4 * g + q];
 
-  // conv1 pixel operand of fragment f: output pixel 16f + r16, kernel row kh
+  // conv1 pixel fragments f = fq + 4i (fragments past 24 compute a clamped
+  // copy and are not stored): output pixel 16f + r16
   int poff[kF1];
 #pragma unroll
   for (int i = 0; i < kF1; ++i) {
-    const int f = wave + kWaves * i;
-    const int p = (f < 25 ? f : 0) * 16 + r16;
+    const int f = fq + 4 * i;
+    const int p = (f < 25 ? f : 24) * 16 + r16;
     poff[i] = ((p / 20) * 4 * kFrame + (p % 20) * 4) * EB;
   }
 
   // ---- S: channels 0..2 of the group's shared stack ----
   const ItemDesc d0 = a.desc[i0];
-  f32x4 S[kF1][2];
+  f32x4 S[kF1];
 #pragma unroll
-  for (int i = 0; i < kF1; ++i) S[i][0] = S[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < kF1; ++i) S[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   {
-    uint4 u0, u1;
-    fload(d0.frame[0], u0, u1);
-    fstore(0, u0, u1);
-    fload(d0.frame[1], u0, u1);
-    __syncthreads();
+    uint4 u;
+    fload(d0.frame[0], u);
+    fstore(0, u);
+    fload(d0.frame[1], u);
+    lds_barrier();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < 2) {                       // stage channel c+1 while using channel c
-        fstore((c + 1) & 1, u0, u1);
-        if (c == 0) fload(d0.frame[2], u0, u1);
+        fstore((c + 1) & 1, u);
+        if (c == 0) fload(d0.frame[2], u);
       }
 #pragma unroll
-      for (int i = 0; i < kF1; ++i) {
-        if (wave + kWaves * i >= 25) continue;
+      for (int i = 0; i < kF1; ++i)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int s = 2 * c + h;
-          const V pv = Fr::ld_pix(&fs[c & 1][poff[i] + (4 * h + g) * kFrame * EB]);
-          S[i][0] = Fr::mma(w1[s][0], pv, S[i][0]);
-          S[i][1] = Fr::mma(w1[s][1], pv, S[i][1]);
-        }
-      }
-      __syncthreads();
+        for (int h = 0; h < 2; ++h)
+          S[i] = Fr::mma(w1[2 * c + h], Fr::ld_pix(&fs[c & 1][poff[i] + (4 * h + g) * kFrame * EB]), S[i]);
+      lds_barrier();
     }
   }
 
   // per-item frames: item k's channel 3 goes to fs[k & 1]
-  uint4 nu0, nu1;
-  fload(a.desc[i0].frame[3], nu0, nu1);
-  fstore(0, nu0, nu1);
-  if (G > 1) fload(a.desc[i0 + 1].frame[3], nu0, nu1);
-  __syncthreads();
+  uint4 nu;
+  fload(a.desc[i0].frame[3], nu);
+  fstore(0, nu);
+  if (G > 1) fload(a.desc[i0 + 1].frame[3], nu);
+  lds_barrier();
 
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
@@ -231,138 +250,140 @@ __global__ void __launch_bounds__(kThreads, (T <= 2 ? 2 : 1)) conv_fused_kernel(
     // ---- conv1: S + channel 3 of each item -> x1 ----
     for (int t = 0; t < nt; ++t) {
       const int k = r0 + t;                               // item within the group
-      if (k + 1 < G) fstore((k + 1) & 1, nu0, nu1);       // next item's frame, other buffer
-      if (k + 2 < G) fload(a.desc[i0 + k + 2].frame[3], nu0, nu1);
+      if (k + 1 < G) fstore((k + 1) & 1, nu);             // next item's frame, other buffer
+      if (k + 2 < G) fload(a.desc[i0 + k + 2].frame[3], nu);
+      pin_vmem_reads();
       const unsigned char* fb = fs[k & 1];
+      const float sc = a.acc_scale[0], o8 = a.out_s8[0];
 #pragma unroll
       for (int i = 0; i < kF1; ++i) {
-        const int f = wave + kWaves * i;
-        if (f >= 25) continue;
-        f32x4 c0 = S[i][0], c1 = S[i][1];
+        f32x4 c0 = S[i];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const V pv = Fr::ld_pix(&fb[poff[i] + (4 * h + g) * kFrame * EB]);
-          c0 = Fr::mma(w1[6 + h][0], pv, c0);
-          c1 = Fr::mma(w1[6 + h][1], pv, c1);
-        }
+        for (int h = 0; h < 2; ++h) c0 = Fr::mma(w1[6 + h], Fr::ld_pix(&fb[poff[i] + (4 * h + g) * kFrame * EB]), c0);
+        const int f = fq + 4 * i;
+        if (f >= 25) continue;                            // wave-uniform: store only
         const int p = f * 16 + r16;
-        const float sc = a.acc_scale[0], o8 = a.out_s8[0];
-        Fr::st4(&x1[x1_off<P>(t, p, 4 * g)], fmaxf(c0[0] * sc + b1[0][0], 0.f), fmaxf(c0[1] * sc + b1[0][1], 0.f),
-                fmaxf(c0[2] * sc + b1[0][2], 0.f), fmaxf(c0[3] * sc + b1[0][3], 0.f), o8);
-        Fr::st4(&x1[x1_off<P>(t, p, 16 + 4 * g)], fmaxf(c1[0] * sc + b1[1][0], 0.f),
-                fmaxf(c1[1] * sc + b1[1][1], 0.f), fmaxf(c1[2] * sc + b1[1][2], 0.f),
-                fmaxf(c1[3] * sc + b1[1][3], 0.f), o8);
+        Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(c0[0] * sc + b1[0], 0.f),
+                fmaxf(c0[1] * sc + b1[1], 0.f), fmaxf(c0[2] * sc + b1[2], 0.f), fmaxf(c0[3] * sc + b1[3], 0.f), o8);
       }
-      __syncthreads();     // x1 item t complete; fs[(k+1)&1] staged for the next item
+      lds_barrier();     // x1 item t complete; fs[(k+1)&1] staged for the next item
     }
 
     // ---- conv2: x1 -> x2 (pixel rows = nt*81) ----
+    // K step s (32 values): kernel row kh = s/4, column kw = s%4, lane group g
+    // holds channels 8g..8g+7, so a lane's operand address is its fragment
+    // base plus a constant of s.  This wave: channel fragments 2*half, +1.
     {
       const int rows = nt * 81;
-      f32x4 acc[F2W][4];
-      int pb[F2W];
+      f32x4 acc[F2W][2];
+      int base[F2W];
       bool ok[F2W];
 #pragma unroll
       for (int i = 0; i < F2W; ++i) {
-        const int r = (wave + kWaves * i) * 16 + r16;
+        const int r = (fq + 4 * i) * 16 + r16;
         ok[i] = r < rows;
         const int rr = ok[i] ? r : 0;
         const int t = rr / 81, p = rr % 81;
-        pb[i] = t * 400 + (p / 9) * 2 * 20 + (p % 9) * 2;     // item-major input pixel
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P + 8 * g * EB;
+        acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      V wc[4], wn[4];
+      V wr[RS][2];
+      auto wload = [&](int s, V (&w)[2]) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) wc[j] = Fr::ld(W2 + ((16 * j + r16) * 512 + 8 * g) * EB);
-#pragma unroll 2
+        for (int j = 0; j < 2; ++j) w[j] = Fr::ld(W2 + ((32 * half + 16 * j + r16) * 512 + 32 * s + 8 * g) * EB);
+      };
+#pragma unroll
+      for (int s = 0; s < RS - 1; ++s) wload(s, wr[s]);
+      pin_vmem_reads();
+#pragma unroll
       for (int s = 0; s < 16; ++s) {
-        if (s + 1 < 16) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) wn[j] = Fr::ld(W2 + ((16 * j + r16) * 512 + 32 * (s + 1) + 8 * g) * EB);
-        }
-        const int U = 4 * s + g, kh = U >> 4, kw = (U >> 2) & 3, cg = U & 3;
+        if (s + RS - 1 < 16) wload(s + RS - 1, wr[(s + RS - 1) % RS]);
+        pin_vmem_reads();
+        const int kh = s >> 2, kw = s & 3;
+        const int koff = ((kh & 1) * 2 + (kw & 1)) * L::X1PH + ((kh >> 1) * 10 + (kw >> 1)) * L::X1P;
 #pragma unroll
         for (int i = 0; i < F2W; ++i) {
-          if (wave + kWaves * i >= F2) continue;
-          const int pp = pb[i] + kh * 20 + kw;             // t*400 + pixel
-          const int t = pp / 400, p = pp - t * 400;
-          const V pv = ok[i] ? Fr::ld(&x1[x1_off<P>(t, p, 8 * cg)]) : V{};
+          const V pv = Fr::ld(&x1[base[i] + koff]);     // clamped address for unused rows
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = Fr::mma(wc[j], pv, acc[i][j]);
+          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[s % RS][j], pv, acc[i][j]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) wc[j] = wn[j];
       }
       const float sc = a.acc_scale[1], o8 = a.out_s8[1];
+      float bb[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[j][q] = a.bias[1][32 * half + 16 * j + 4 * g + q];
 #pragma unroll
       for (int i = 0; i < F2W; ++i) {
-        if (wave + kWaves * i >= F2 || !ok[i]) continue;
-        const int r = (wave + kWaves * i) * 16 + r16;
+        if (!ok[i]) continue;
+        const int r = (fq + 4 * i) * 16 + r16;
         const int t = r / 81, p = r % 81;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int n = 16 * j + 4 * g;
-          Fr::st4(&x2[x2_off<P>(t, p, n)], fmaxf(acc[i][j][0] * sc + a.bias[1][n], 0.f),
-                  fmaxf(acc[i][j][1] * sc + a.bias[1][n + 1], 0.f), fmaxf(acc[i][j][2] * sc + a.bias[1][n + 2], 0.f),
-                  fmaxf(acc[i][j][3] * sc + a.bias[1][n + 3], 0.f), o8);
-        }
+        for (int j = 0; j < 2; ++j)
+          Fr::st4(&x2[L::x2(t, p, 32 * half + 16 * j + 4 * g)], fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
+                  fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
+                  fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- conv3: x2 -> x3 (HBM, channels-last [item][49][64]) ----
+    // K step s: kernel tap kk = s/2 (kh = kk/3, kw = kk%3), channels
+    // 32(s&1) + 8g .. +7.
     {
       const int rows = nt * 49;
-      f32x4 acc[F3W][4];
-      int pb[F3W];
+      f32x4 acc[F3W][2];
+      int base[F3W], pt[F3W];
       bool ok[F3W];
 #pragma unroll
       for (int i = 0; i < F3W; ++i) {
-        const int r = (wave + kWaves * i) * 16 + r16;
+        const int r = (fq + 4 * i) * 16 + r16;
         ok[i] = r < rows;
         const int rr = ok[i] ? r : 0;
-        const int t = rr / 49, p = rr % 49;
-        pb[i] = t * 81 + (p / 7) * 9 + (p % 7);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int p = rr % 49;
+        pt[i] = rr / 49;
+        base[i] = pt[i] * L::X2T + ((p / 7) * 9 + (p % 7)) * L::X2P + 8 * g * EB;
+        acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      V wc[4], wn[4];
+      V wr[RS][2];
+      auto wload = [&](int s, V (&w)[2]) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) wc[j] = Fr::ld(W3 + ((16 * j + r16) * 576 + 8 * g) * EB);
-#pragma unroll 2
+        for (int j = 0; j < 2; ++j) w[j] = Fr::ld(W3 + ((32 * half + 16 * j + r16) * 576 + 32 * s + 8 * g) * EB);
+      };
+#pragma unroll
+      for (int s = 0; s < RS - 1; ++s) wload(s, wr[s]);
+      pin_vmem_reads();
+#pragma unroll
       for (int s = 0; s < 18; ++s) {
-        if (s + 1 < 18) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) wn[j] = Fr::ld(W3 + ((16 * j + r16) * 576 + 32 * (s + 1) + 8 * g) * EB);
-        }
-        const int U = 4 * s + g, kk = U >> 3, cg = U & 7;
+        if (s + RS - 1 < 18) wload(s + RS - 1, wr[(s + RS - 1) % RS]);
+        pin_vmem_reads();
+        const int kk = s >> 1;
+        const int koff = ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (s & 1) * EB;
 #pragma unroll
         for (int i = 0; i < F3W; ++i) {
-          if (wave + kWaves * i >= F3) continue;
-          const int pp = pb[i] + (kk / 3) * 9 + kk % 3;     // t*81 + pixel
-          const int t = pp / 81, p = pp - t * 81;
-          const V pv = ok[i] ? Fr::ld(&x2[x2_off<P>(t, p, 8 * cg)]) : V{};
+          const V pv = Fr::ld(&x2[base[i] + koff]);     // clamped address for unused rows
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = Fr::mma(wc[j], pv, acc[i][j]);
+          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[s % RS][j], pv, acc[i][j]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) wc[j] = wn[j];
       }
       const float sc = a.acc_scale[2], o8 = a.out_s8[2];
+      float bb[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[j][q] = a.bias[2][32 * half + 16 * j + 4 * g + q];
       const long long item_first = i0 + r0;
 #pragma unroll
       for (int i = 0; i < F3W; ++i) {
-        if (wave + kWaves * i >= F3 || !ok[i]) continue;
-        const int r = (wave + kWaves * i) * 16 + r16;
-        const long long row = (item_first + r / 49) * 49 + r % 49;
+        if (!ok[i]) continue;
+        const int r = (fq + 4 * i) * 16 + r16;
+        const long long row = (item_first + pt[i]) * 49 + (r - pt[i] * 49);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int n = 16 * j + 4 * g;
-          Fr::st4(X3 + (row * 64 + n) * EB, fmaxf(acc[i][j][0] * sc + a.bias[2][n], 0.f),
-                  fmaxf(acc[i][j][1] * sc + a.bias[2][n + 1], 0.f), fmaxf(acc[i][j][2] * sc + a.bias[2][n + 2], 0.f),
-                  fmaxf(acc[i][j][3] * sc + a.bias[2][n + 3], 0.f), o8);
-        }
+        for (int j = 0; j < 2; ++j)
+          Fr::st4(X3 + (row * 64 + 32 * half + 16 * j + 4 * g) * EB, fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
+                  fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
+                  fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
     }
     // No barrier needed here: the next round's conv1 writes x1 (last read by
