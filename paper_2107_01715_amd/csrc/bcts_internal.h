@@ -110,6 +110,11 @@ struct QnetDev {
   float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
 };
 
+// fc1 as a 256 x 128-tiled MFMA GEMM (BF16 / FP8): h = ReLU(acc_scale *
+// x3 W^T + b) in the operand type (FP8 outputs scaled by out_s8).
+void launch_fc1_mfma(int prec, long long n, const void* x3, const void* w, const float* bias, float acc_scale,
+                     float out_s8, void* h, hipStream_t s);
+
 // fc1 (+ReLU) and fc2 (+max over A, root rows of Q_0) over a chunk whose
 // conv3 output x3 is ready; `h` holds [n][512] in the operand type.
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,

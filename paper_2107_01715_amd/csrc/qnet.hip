@@ -487,7 +487,8 @@ void run_fc(const QnetDev& q, const ItemDesc* desc, long long n, const void* x3,
   a.desc = desc;
   a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3);
   a.out_s8 = P == P_FP8 ? q.ascale[4] : 1.f; a.out = h;
-  run_layer<3, P>(a, s);
+  if (P == P_FP32) run_layer<3, P>(a, s);
+  else launch_fc1_mfma(P, n, x3, wp(3), q.b[3], accs(3), a.out_s8, h, s);
   if (ev) (void)hipEventRecord(ev, s);
   a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
   run_layer<4, P>(a, s);
