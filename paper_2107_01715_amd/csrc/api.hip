@@ -414,7 +414,8 @@ bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameB
     fa.desc = desc;
     const bool f8 = c->prec == P_FP8;
     for (int l = 0; l < 3; ++l) {
-      fa.w[l] = f8 ? (const void*)q.w8[l] : (const void*)q.wb[l];
+      // conv1 in GEMM layout, conv2 / conv3 fragment-major
+      fa.w[l] = l == 0 ? (f8 ? (const void*)q.w8[0] : (const void*)q.wb[0]) : (f8 ? q.wf8[l] : q.wfb[l]);
       fa.bias[l] = q.b[l];
       fa.acc_scale[l] = f8 ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
       fa.out_s8[l] = f8 ? q.ascale[l + 1] : 1.f;
@@ -897,13 +898,16 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
   std::memcpy(B[3].data(), f1b, sizeof(float) * 512);
   std::memcpy(B[4].data(), f2b, sizeof(float) * 18);
 
-  size_t off[5][4], o = 0;   // fp32 w, bf16 w, fp8 w, bias
+  // fp32 w, bf16 w, fp8 w, bias, and for conv2 / conv3 fragment-major bf16 and fp8 copies
+  size_t off[5][6], o = 0;
   for (int l = 0; l < 5; ++l) {
     const size_t n = W[l].size();
     off[l][0] = o; o += align_up(n * 4);
     off[l][1] = o; o += align_up(n * 2);
     off[l][2] = o; o += align_up(n);
     off[l][3] = o; o += align_up(B[l].size() * 4);
+    off[l][4] = o; o += (l == 1 || l == 2) ? align_up(n * 2) : 0;
+    off[l][5] = o; o += (l == 1 || l == 2) ? align_up(n) : 0;
   }
   if (c->wmem) {
     HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -927,6 +931,13 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
     launch_convert_bf16(c->q.w[l], const_cast<uint16_t*>(c->q.wb[l]), (long long)W[l].size(), c->stream);
     launch_convert_fp8(c->q.w[l], const_cast<uint8_t*>(c->q.w8[l]), (long long)W[l].size(), c->q.wscale[l],
                        c->stream);
+    c->q.wfb[l] = c->q.wf8[l] = nullptr;
+    if (l == 1 || l == 2) {
+      c->q.wfb[l] = base + off[l][4];
+      c->q.wf8[l] = base + off[l][5];
+      launch_fragment_major(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, c->stream);
+      launch_fragment_major(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, c->stream);
+    }
   }
   // activation scales until calibrated: pixels 1:1 (255 -> 256 in e4m3), others unit
   c->q.ascale[0] = 1.f;

@@ -87,7 +87,7 @@ struct FusedConvArgs {
   const FusedGroup* groups;    // groups of this chunk
   long long item_base;         // plan-global index of desc[0]
   const ItemDesc* desc;        // chunk-relative item descriptors
-  const void* w[3];            // conv weights in operand type, GEMM layout [N][K]
+  const void* w[3];            // conv weights in operand type: conv1 [N][K], conv2/conv3 fragment-major
   const float* bias[3];
   float acc_scale[3];          // accumulator scale (1/255 on conv1; fp8 operand scales)
   float out_s8[3];             // fp8: input scale of the next layer
@@ -108,7 +108,14 @@ struct QnetDev {
   const float* b[5];           // biases, fp32
   float wscale[5];             // fp8 weight scale: w8 = e4m3(w * wscale)
   float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
+  // conv2 / conv3 (index 1, 2) in fragment-major order for the fused kernel:
+  // unit (cf, s, lane) = the 8 operand elements W[16cf + lane%16][32s + 8(lane/16) ..]
+  const void* wfb[5];          // bf16
+  const void* wf8[5];          // e4m3
 };
+
+// Copies W[N][K] (element size eb bytes) into fragment-major order.
+void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hipStream_t s);
 
 // fc1 as a 256 x 128-tiled MFMA GEMM (BF16 / FP8): h = ReLU(acc_scale *
 // x3 W^T + b) in the operand type (FP8 outputs scaled by out_s8).

@@ -39,6 +39,9 @@ typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 constexpr int kThreads = 512;          // 8 wavefronts
 constexpr int kF1 = 7;                 // conv1 pixel fragments per wave: (w>>1) + 4i
+constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
+constexpr int kD = 5;                  // weight lookahead in K steps
+constexpr int kRing = kD + 1;
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -83,6 +86,10 @@ template <> struct F<P_BF16> {
     return *reinterpret_cast<const V*>(&u);
   }
   __device__ static f32x4 mma(V a, V b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+  // one lane's weight operand through a buffer resource: byte offset voff + soff
+  __device__ static V ldw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
   // 16 raw pixels -> 16 operands in LDS (32 bytes)
   __device__ static void stage16(unsigned char* dst, uint4 raw, float) {
     const unsigned w[4] = {raw.x, raw.y, raw.z, raw.w};
@@ -114,6 +121,9 @@ template <> struct F<P_FP8> {
     return (long)(((unsigned long long)b << 32) | a);
   }
   __device__ static f32x4 mma(V a, V b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+  __device__ static V ldw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
   __device__ static void stage16(unsigned char* dst, uint4 raw, float s8) {
     const unsigned w[4] = {raw.x, raw.y, raw.z, raw.w};
     unsigned o[4];
@@ -158,7 +168,6 @@ template <int P> struct Lay {
 // from L2 two K steps ahead.
 template <int P, int T>
 __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
-  constexpr int RS = 3;     // weight ring: RS-1 K steps ahead
   typedef F<P> Fr;
   typedef typename Fr::V V;
   constexpr int EB = Fr::EB;
@@ -177,8 +186,27 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   const int r16 = lane & 15, g = lane >> 4;
   const int half = wave & 1, fq = wave >> 1;      // channel half, first pixel fragment
   const unsigned char* W1 = reinterpret_cast<const unsigned char*>(a.w[0]);
-  const unsigned char* W2 = reinterpret_cast<const unsigned char*>(a.w[1]);
-  const unsigned char* W3 = reinterpret_cast<const unsigned char*>(a.w[2]);
+  // conv2 / conv3 weights, fragment-major: the A operand of channel
+  // fragment cf at K step s is 64 lanes x 8 elements, contiguous.  They are
+  // read through buffer resources so that a step's offset is a scalar: the
+  // only per-lane address is the lane offset within this wave's fragments.
+  constexpr int FB = 64 * 8 * EB;                       // bytes per weight fragment
+  const __amdgpu_buffer_rsrc_t W2r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.w[1]), (short)0, 64 * 512 * EB, 0x00020000);
+  const __amdgpu_buffer_rsrc_t W3r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.w[2]), (short)0, 64 * 576 * EB, 0x00020000);
+  const int v2 = half * 2 * 16 * FB + lane * 8 * EB;    // channel fragments 2*half, +1
+  const int v3 = half * 2 * 18 * FB + lane * 8 * EB;
+  // weight step u of the conv2 -> conv3 sequence: this wave's 2 channel fragments
+  auto wstep = [&](int u, V (&w)[2]) {
+    if (u < 16) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) w[j] = Fr::ldw(W2r, v2, (j * 16 + u) * FB);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) w[j] = Fr::ldw(W3r, v3, (j * 18 + u - 16) * FB);
+    }
+  };
   unsigned char* X3 = reinterpret_cast<unsigned char*>(a.x3);
   const float s8 = a.pix_s8;
 
@@ -246,6 +274,10 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
+    // the first kD weight steps of conv2 load while conv1 runs
+    V wr[kRing][2];
+#pragma unroll
+    for (int u = 0; u < kD; ++u) wstep(u, wr[u % kRing]);
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
     for (int t = 0; t < nt; ++t) {
@@ -269,44 +301,47 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       lds_barrier();     // x1 item t complete; fs[(k+1)&1] staged for the next item
     }
 
-    // ---- conv2: x1 -> x2 (pixel rows = nt*81) ----
-    // K step s (32 values): kernel row kh = s/4, column kw = s%4, lane group g
-    // holds channels 8g..8g+7, so a lane's operand address is its fragment
-    // base plus a constant of s.  This wave: channel fragments 2*half, +1.
+    // ---- conv2 (x1 -> x2) and conv3 (x2 -> x3) ----
+    // The K steps of both layers form one sequence u = 0..33 (conv2 steps
+    // 0..15, conv3 steps 16..33).  Weight fragments stream from L2 kD steps
+    // ahead through a register ring that runs across the layer boundary;
+    // pixel fragments are read from LDS one step ahead.  A full scheduling
+    // barrier between steps keeps every load at its issue point.
     {
-      const int rows = nt * 81;
+      const int rows2 = nt * 81;
       f32x4 acc[F2W][2];
       int base[F2W];
       bool ok[F2W];
 #pragma unroll
       for (int i = 0; i < F2W; ++i) {
         const int r = (fq + 4 * i) * 16 + r16;
-        ok[i] = r < rows;
+        ok[i] = r < rows2;
         const int rr = ok[i] ? r : 0;
         const int t = rr / 81, p = rr % 81;
         base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P + 8 * g * EB;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      V wr[RS][2];
-      auto wload = [&](int s, V (&w)[2]) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) w[j] = Fr::ld(W2 + ((32 * half + 16 * j + r16) * 512 + 32 * s + 8 * g) * EB);
+      // conv2 K step s: kernel row kh = s/4, column kw = s%4; lane group g
+      // holds input channels 8g..8g+7 of that tap
+      auto koff2 = [](int s) {
+        const int kh = s >> 2, kw = s & 3;
+        return ((kh & 1) * 2 + (kw & 1)) * L::X1PH + ((kh >> 1) * 10 + (kw >> 1)) * L::X1P;
       };
+      V pv[2][F2W];
 #pragma unroll
-      for (int s = 0; s < RS - 1; ++s) wload(s, wr[s]);
-      pin_vmem_reads();
+      for (int i = 0; i < F2W; ++i) pv[0][i] = Fr::ld(&x1[base[i] + koff2(0)]);
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        if (s + RS - 1 < 16) wload(s + RS - 1, wr[(s + RS - 1) % RS]);
-        pin_vmem_reads();
-        const int kh = s >> 2, kw = s & 3;
-        const int koff = ((kh & 1) * 2 + (kw & 1)) * L::X1PH + ((kh >> 1) * 10 + (kw >> 1)) * L::X1P;
+        if (s + kD < kSteps) wstep(s + kD, wr[(s + kD) % kRing]);
+        if (s + 1 < 16) {
 #pragma unroll
-        for (int i = 0; i < F2W; ++i) {
-          const V pv = Fr::ld(&x1[base[i] + koff]);     // clamped address for unused rows
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[s % RS][j], pv, acc[i][j]);
+          for (int i = 0; i < F2W; ++i) pv[(s + 1) & 1][i] = Fr::ld(&x1[base[i] + koff2(s + 1)]);  // clamped rows
         }
+#pragma unroll
+        for (int i = 0; i < F2W; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[s % kRing][j], pv[s & 1][i], acc[i][j]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       const float sc = a.acc_scale[1], o8 = a.out_s8[1];
       float bb[2][4];
@@ -327,45 +362,43 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       }
     }
     lds_barrier();
-
-    // ---- conv3: x2 -> x3 (HBM, channels-last [item][49][64]) ----
-    // K step s: kernel tap kk = s/2 (kh = kk/3, kw = kk%3), channels
-    // 32(s&1) + 8g .. +7.
     {
-      const int rows = nt * 49;
+      // conv3 K step s: kernel tap kk = s/2 (kh = kk/3, kw = kk%3),
+      // channels 32(s&1) + 8g .. +7; output to HBM, channels-last [item][49][64]
+      const int rows3 = nt * 49;
       f32x4 acc[F3W][2];
       int base[F3W], pt[F3W];
       bool ok[F3W];
 #pragma unroll
       for (int i = 0; i < F3W; ++i) {
         const int r = (fq + 4 * i) * 16 + r16;
-        ok[i] = r < rows;
+        ok[i] = r < rows3;
         const int rr = ok[i] ? r : 0;
         const int p = rr % 49;
         pt[i] = rr / 49;
         base[i] = pt[i] * L::X2T + ((p / 7) * 9 + (p % 7)) * L::X2P + 8 * g * EB;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      V wr[RS][2];
-      auto wload = [&](int s, V (&w)[2]) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) w[j] = Fr::ld(W3 + ((32 * half + 16 * j + r16) * 576 + 32 * s + 8 * g) * EB);
+      auto koff3 = [](int s) {
+        const int kk = s >> 1;
+        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (s & 1) * EB;
       };
+      V pv[2][F3W];
 #pragma unroll
-      for (int s = 0; s < RS - 1; ++s) wload(s, wr[s]);
-      pin_vmem_reads();
+      for (int i = 0; i < F3W; ++i) pv[0][i] = Fr::ld(&x2[base[i] + koff3(0)]);
 #pragma unroll
       for (int s = 0; s < 18; ++s) {
-        if (s + RS - 1 < 18) wload(s + RS - 1, wr[(s + RS - 1) % RS]);
-        pin_vmem_reads();
-        const int kk = s >> 1;
-        const int koff = ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (s & 1) * EB;
+        const int u = 16 + s;
+        if (u + kD < kSteps) wstep(u + kD, wr[(u + kD) % kRing]);
+        if (s + 1 < 18) {
 #pragma unroll
-        for (int i = 0; i < F3W; ++i) {
-          const V pv = Fr::ld(&x2[base[i] + koff]);     // clamped address for unused rows
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[s % RS][j], pv, acc[i][j]);
+          for (int i = 0; i < F3W; ++i) pv[(s + 1) & 1][i] = Fr::ld(&x2[base[i] + koff3(s + 1)]);  // clamped rows
         }
+#pragma unroll
+        for (int i = 0; i < F3W; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wr[u % kRing][j], pv[s & 1][i], acc[i][j]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       const float sc = a.acc_scale[2], o8 = a.out_s8[2];
       float bb[2][4];
@@ -393,7 +426,27 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   }
 }
 
+// Fragment-major copy of W[N][K]: unit u = (cf, s, lane) receives the 8
+// elements W[16cf + lane%16][32s + 8(lane/16) .. +7].
+__global__ void fragment_major_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int N,
+                                      int K, int eb) {
+  const int NS = K / 32;
+  const long long units = (long long)(N / 16) * NS * 64;
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= units) return;
+  const int lane = (int)(u % 64), s = (int)((u / 64) % NS), cf = (int)(u / 64 / NS);
+  const unsigned char* sp = src + ((long long)(16 * cf + lane % 16) * K + 32 * s + 8 * (lane / 16)) * eb;
+  unsigned char* dp = dst + u * 8 * eb;
+  for (int b = 0; b < 8 * eb; ++b) dp[b] = sp[b];
+}
+
 }  // namespace
+
+void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hipStream_t s) {
+  const long long units = (long long)(N / 16) * (K / 32) * 64;
+  hipLaunchKernelGGL(fragment_major_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), N, K, eb);
+}
 
 void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s) {
   if (n_groups <= 0) return;
