@@ -42,6 +42,7 @@ constexpr int kF1 = 7;                 // conv1 pixel fragments per wave: (w>>1)
 constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
+constexpr int kMaxGroup = 32;          // sibling group size bound (A <= 18)
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -175,9 +176,13 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   constexpr int R2 = T * 81, F2 = (R2 + 15) / 16, F2W = (F2 + 3) / 4;
   constexpr int R3 = T * 49, F3 = (R3 + 15) / 16, F3W = (F3 + 3) / 4;
   typedef Lay<P> L;
+  // x1 of the round's items; ux holds the round's input frames during conv1
+  // and x2 from conv2's epilogue to the end of conv3 (never both at once)
+  constexpr int NFR = T > 3 ? T : 3;                    // frames staged at once
+  constexpr int UXB = (T * L::X2T > NFR * FRB) ? T * L::X2T : NFR * FRB;
   __shared__ __attribute__((aligned(16))) unsigned char x1[T * L::X1T];
-  __shared__ __attribute__((aligned(16))) unsigned char x2[T * L::X2T];
-  __shared__ __attribute__((aligned(16))) unsigned char fs[2][FRB];
+  __shared__ __attribute__((aligned(16))) unsigned char ux[UXB];
+  __shared__ const uint8_t* fptr[kMaxGroup];            // channel-3 frame of each item of the group
 
   const FusedGroup grp = a.groups[blockIdx.x];
   const int G = grp.count;
@@ -210,13 +215,13 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   unsigned char* X3 = reinterpret_cast<unsigned char*>(a.x3);
   const float s8 = a.pix_s8;
 
-  // frame staging: 441 16-byte chunks, one per thread
+  // frames: 441 16-byte chunks, one per thread; threads past the last chunk
+  // load a valid duplicate (no branch around the load) and stage nothing
   const bool cf = tid < kFrameBytes / 16;
-  auto fload = [&](const uint8_t* fr, uint4& u) {
-    if (cf) u = reinterpret_cast<const uint4*>(fr)[tid];
-  };
-  auto fstore = [&](int buf, const uint4& u) {
-    if (cf) Fr::stage16(&fs[buf][tid * 16 * EB], u, s8);
+  const int ck = cf ? tid : kFrameBytes / 16 - 1;
+  auto fload = [&](const uint8_t* fr) { return reinterpret_cast<const uint4*>(fr)[ck]; };
+  auto fstage = [&](int slot, const uint4& u) {
+    if (cf) Fr::stage16(&ux[slot * FRB + tid * 16 * EB], u, s8);
   };
 
   // conv1 weights (A operand) of this wave's channel half: K step s covers
@@ -240,66 +245,72 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   }
 
   // ---- S: channels 0..2 of the group's shared stack ----
+  // The shared frames and the first round's frames are requested together;
+  // later rounds' frames load into registers one round ahead.
   const ItemDesc d0 = a.desc[i0];
+  if (tid < G) fptr[tid] = a.desc[i0 + tid].frame[3];
+  uint4 fv[T];
+  {
+    uint4 sv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sv[c] = fload(d0.frame[c]);
+#pragma unroll
+    for (int t = 0; t < T; ++t) fv[t] = fload(a.desc[i0 + (t < G ? t : G - 1)].frame[3]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fstage(c, sv[c]);
+  }
+  lds_barrier();
   f32x4 S[kF1];
 #pragma unroll
   for (int i = 0; i < kF1; ++i) S[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  {
-    uint4 u;
-    fload(d0.frame[0], u);
-    fstore(0, u);
-    fload(d0.frame[1], u);
-    lds_barrier();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (c < 2) {                       // stage channel c+1 while using channel c
-        fstore((c + 1) & 1, u);
-        if (c == 0) fload(d0.frame[2], u);
-      }
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int i = 0; i < kF1; ++i)
+    for (int i = 0; i < kF1; ++i)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          S[i] = Fr::mma(w1[2 * c + h], Fr::ld_pix(&fs[c & 1][poff[i] + (4 * h + g) * kFrame * EB]), S[i]);
-      lds_barrier();
-    }
-  }
-
-  // per-item frames: item k's channel 3 goes to fs[k & 1]
-  uint4 nu;
-  fload(a.desc[i0].frame[3], nu);
-  fstore(0, nu);
-  if (G > 1) fload(a.desc[i0 + 1].frame[3], nu);
-  lds_barrier();
+      for (int h = 0; h < 2; ++h)
+        S[i] = Fr::mma(w1[2 * c + h], Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]), S[i]);
 
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
+    lds_barrier();       // ux is free: the S reads or the previous round's conv3 reads are done
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      if (t < nt) fstage(t, fv[t]);
+    // next round's frames (items past the group load the last item's frame, unused)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int k = r0 + T + t;
+      fv[t] = fload(fptr[k < G ? k : G - 1]);
+    }
     // the first kD weight steps of conv2 load while conv1 runs
     V wr[kRing][2];
 #pragma unroll
     for (int u = 0; u < kD; ++u) wstep(u, wr[u % kRing]);
+    lds_barrier();       // the round's frames are staged
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
-    for (int t = 0; t < nt; ++t) {
-      const int k = r0 + t;                               // item within the group
-      if (k + 1 < G) fstore((k + 1) & 1, nu);             // next item's frame, other buffer
-      if (k + 2 < G) fload(a.desc[i0 + k + 2].frame[3], nu);
-      pin_vmem_reads();
-      const unsigned char* fb = fs[k & 1];
+    {
       const float sc = a.acc_scale[0], o8 = a.out_s8[0];
 #pragma unroll
-      for (int i = 0; i < kF1; ++i) {
-        f32x4 c0 = S[i];
+      for (int t = 0; t < T; ++t) {
+        if (t >= nt) break;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) c0 = Fr::mma(w1[6 + h], Fr::ld_pix(&fb[poff[i] + (4 * h + g) * kFrame * EB]), c0);
-        const int f = fq + 4 * i;
-        if (f >= 25) continue;                            // wave-uniform: store only
-        const int p = f * 16 + r16;
-        Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(c0[0] * sc + b1[0], 0.f),
-                fmaxf(c0[1] * sc + b1[1], 0.f), fmaxf(c0[2] * sc + b1[2], 0.f), fmaxf(c0[3] * sc + b1[3], 0.f), o8);
+        for (int i = 0; i < kF1; ++i) {
+          f32x4 c0 = S[i];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            c0 = Fr::mma(w1[6 + h], Fr::ld_pix(&ux[t * FRB + poff[i] + (4 * h + g) * kFrame * EB]), c0);
+          const int f = fq + 4 * i;
+          if (f >= 25) continue;                          // wave-uniform: store only
+          const int p = f * 16 + r16;
+          Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(c0[0] * sc + b1[0], 0.f),
+                  fmaxf(c0[1] * sc + b1[1], 0.f), fmaxf(c0[2] * sc + b1[2], 0.f), fmaxf(c0[3] * sc + b1[3], 0.f),
+                  o8);
+        }
       }
-      lds_barrier();     // x1 item t complete; fs[(k+1)&1] staged for the next item
     }
+    lds_barrier();       // x1 complete, frame reads done: conv2's epilogue may overwrite ux
 
     // ---- conv2 (x1 -> x2) and conv3 (x2 -> x3) ----
     // The K steps of both layers form one sequence u = 0..33 (conv2 steps
@@ -356,7 +367,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         const int t = r / 81, p = r % 81;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          Fr::st4(&x2[L::x2(t, p, 32 * half + 16 * j + 4 * g)], fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
+          Fr::st4(&ux[L::x2(t, p, 32 * half + 16 * j + 4 * g)], fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
                   fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
                   fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
@@ -385,14 +396,14 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       };
       V pv[2][F3W];
 #pragma unroll
-      for (int i = 0; i < F3W; ++i) pv[0][i] = Fr::ld(&x2[base[i] + koff3(0)]);
+      for (int i = 0; i < F3W; ++i) pv[0][i] = Fr::ld(&ux[base[i] + koff3(0)]);
 #pragma unroll
       for (int s = 0; s < 18; ++s) {
         const int u = 16 + s;
         if (u + kD < kSteps) wstep(u + kD, wr[(u + kD) % kRing]);
         if (s + 1 < 18) {
 #pragma unroll
-          for (int i = 0; i < F3W; ++i) pv[(s + 1) & 1][i] = Fr::ld(&x2[base[i] + koff3(s + 1)]);  // clamped rows
+          for (int i = 0; i < F3W; ++i) pv[(s + 1) & 1][i] = Fr::ld(&ux[base[i] + koff3(s + 1)]);  // clamped rows
         }
 #pragma unroll
         for (int i = 0; i < F3W; ++i)
@@ -419,10 +430,8 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
                   fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
     }
-    // No barrier needed here: the next round's conv1 writes x1 (last read by
-    // conv2, before the barrier above) and fs (its own per-item barriers);
-    // x2 is rewritten only after the next round's conv1 barriers, which every
-    // wave reaches after its conv3 reads.
+    // The next round starts with a barrier before it stages frames into ux;
+    // x1 was last read by conv2, before the barrier above.
   }
 }
 
