@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   __shared__ __attribute__((aligned(16))) unsigned char x1[T * L::X1T];
   __shared__ __attribute__((aligned(16))) unsigned char ux[UXB];
   __shared__ const uint8_t* fptr[kMaxGroup];            // channel-3 frame of each item of the group
+  __shared__ __attribute__((aligned(16))) float sbias[2][64];   // conv2, conv3 biases
 
   const FusedGroup grp = a.groups[blockIdx.x];
   const int G = grp.count;
@@ -216,13 +217,19 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   const float s8 = a.pix_s8;
 
   // frames: 441 16-byte chunks, one per thread; threads past the last chunk
-  // load a valid duplicate (no branch around the load) and stage nothing
+  // load and stage a duplicate of the last chunk (identical bytes to the
+  // same LDS address), so neither the load nor its use sits behind a branch
   const bool cf = tid < kFrameBytes / 16;
   const int ck = cf ? tid : kFrameBytes / 16 - 1;
-  auto fload = [&](const uint8_t* fr) { return reinterpret_cast<const uint4*>(fr)[ck]; };
-  auto fstage = [&](int slot, const uint4& u) {
-    if (cf) Fr::stage16(&ux[slot * FRB + tid * 16 * EB], u, s8);
+  // (frame pointers come from memory, so they are generic; the cast makes
+  // these global loads, which the LDS-only barrier's lgkmcnt wait ignores;
+  // a flat load would be counted there too and end the prefetch early)
+  auto fload = [&](const uint8_t* fr) {
+    typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+    const u32x4 v = ((const __attribute__((address_space(1))) u32x4*)fr)[ck];
+    return make_uint4(v[0], v[1], v[2], v[3]);
   };
+  auto fstage = [&](int slot, const uint4& u) { Fr::stage16(&ux[slot * FRB + ck * 16 * EB], u, s8); };
 
   // conv1 weights (A operand) of this wave's channel half: K step s covers
   // stack channel s/2, kernel rows 4(s&1)..+3; lane group g holds kernel row
@@ -246,9 +253,11 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 
   // ---- S: channels 0..2 of the group's shared stack ----
   // The shared frames and the first round's frames are requested together;
-  // later rounds' frames load into registers one round ahead.
+  // a later round's frames load into registers during the previous round's
+  // conv2/conv3 and are staged at its end.
   const ItemDesc d0 = a.desc[i0];
   if (tid < G) fptr[tid] = a.desc[i0 + tid].frame[3];
+  if (tid < 128) sbias[tid >> 6][tid & 63] = a.bias[1 + (tid >> 6)][tid & 63];
   uint4 fv[T];
   {
     uint4 sv[3];
@@ -271,18 +280,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       for (int h = 0; h < 2; ++h)
         S[i] = Fr::mma(w1[2 * c + h], Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]), S[i]);
 
+  lds_barrier();         // the S reads are done
+#pragma unroll
+  for (int t = 0; t < T; ++t) fstage(t, fv[t]);
+
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
-    lds_barrier();       // ux is free: the S reads or the previous round's conv3 reads are done
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-      if (t < nt) fstage(t, fv[t]);
-    // next round's frames (items past the group load the last item's frame, unused)
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int k = r0 + T + t;
-      fv[t] = fload(fptr[k < G ? k : G - 1]);
-    }
     // the first kD weight steps of conv2 load while conv1 runs
     V wr[kRing][2];
 #pragma unroll
@@ -311,6 +314,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       }
     }
     lds_barrier();       // x1 complete, frame reads done: conv2's epilogue may overwrite ux
+    // next round's frames (items past the group load the last item's frame, unused)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int k = r0 + T + t;
+      fv[t] = fload(fptr[k < G ? k : G - 1]);
+    }
 
     // ---- conv2 (x1 -> x2) and conv3 (x2 -> x3) ----
     // The K steps of both layers form one sequence u = 0..33 (conv2 steps
@@ -359,7 +368,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[j][q] = a.bias[1][32 * half + 16 * j + 4 * g + q];
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[0][32 * half + 16 * j + 4 * g + q];
 #pragma unroll
       for (int i = 0; i < F2W; ++i) {
         if (!ok[i]) continue;
@@ -416,7 +425,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[j][q] = a.bias[2][32 * half + 16 * j + 4 * g + q];
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[1][32 * half + 16 * j + 4 * g + q];
       const long long item_first = i0 + r0;
 #pragma unroll
       for (int i = 0; i < F3W; ++i) {
@@ -430,8 +439,10 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
                   fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
     }
-    // The next round starts with a barrier before it stages frames into ux;
-    // x1 was last read by conv2, before the barrier above.
+    lds_barrier();       // conv3's reads of x2 are done: ux takes the next round's frames
+#pragma unroll
+    for (int t = 0; t < T; ++t) fstage(t, fv[t]);
+    // x1 was last read by conv2, before the barrier after conv2's epilogue
   }
 }
 
