@@ -17,7 +17,17 @@ Reported beside the headline (BF16, batched):
     the dominant kernel, p50/p99 step latency;
   * the FP64 oracle timed on the host cores over a bounded sample.
 
+Two further workloads print their own JSON line:
+  --workload mixed  1,024 roots with A in {4,6,18} and depth in {1,2,3}
+                    (seeded) plus 8 roots at A=6, depth 4, BF16, the whole
+                    batch as one captured HIP graph replayed per step;
+  --workload serve  Poisson arrivals at 2000 requests/s for 60 s (A in
+                    {4,6,18}, depth 1-4), BF16, continuous batching through
+                    submit/progress/poll; p50/p99 request latency after a
+                    5 s warm-up, plus a run under a 1 GB device budget.
+
     python bench.py [--steps K] [--warmup W] [--precision bf16|fp8|fp32]
+                    [--workload headline|mixed|serve]
 """
 from __future__ import annotations
 
@@ -39,7 +49,8 @@ HBM_PEAK_GBS = 8000.0
 LAYER_FLOPS = {"conv1": 2 * 400 * 32 * 256, "conv2": 2 * 81 * 64 * 512, "conv3": 2 * 49 * 64 * 576,
                "fc1": 2 * 512 * 3136, "fc2": 2 * A * 512}
 LAYER_KERNEL = {"conv1": "layer_kernel<0,P>", "conv2": "layer_kernel<1,P>", "conv3": "layer_kernel<2,P>",
-                "fc1": "layer_kernel<3,P>", "fc2": "layer_kernel<4,P>", "conv_fused": "conv_fused_kernel<P,T>"}
+                "fc1": "fc1_kernel<P>", "fc2": "layer_kernel<4,P>", "conv_fused": "conv_fused_kernel<P,T>"}
+MIXED_SEED, SERVE_SEED = 1004, 1005
 # algorithmic bytes per new node written by the expansion: frame, positions, return, reward
 EXPAND_BYTES_PER_NODE = 7056 + 16 + 4 + 1
 
@@ -84,6 +95,157 @@ def agreement(act, q, ref):
             "max_rel_err": max(errs), "mean_rel_err": float(np.mean(errs))}
 
 
+def _setup(seed, n_roots, budget=0):
+    """Context with the workload's env, weights and FP8 calibration."""
+    from paper_2107_01715_amd import bcts, workload as W
+    ep = W.env_params(seed)
+    ctx = bcts.Context(0, budget)
+    ctx.set_env(ep.delta, ep.vel)
+    ctx.set_qnet(W.qnet_blob(W.qnet_weights(WEIGHT_SEED)))
+    _, cal = W.roots(CALIB_SEED, 64)
+    ctx.calibrate_fp8(cal)
+    return ctx
+
+
+def run_mixed(args):
+    """Mixed batch: 1,024 roots (A ~ U{4,6,18}, d ~ U{1,2,3}) + 8 roots at
+    A=6, d=4, searched together as one captured HIP graph per step."""
+    import numpy as np
+    import torch
+    from paper_2107_01715_amd import bcts, workload as W
+    A_mix, d_mix = W.mixed_shapes(MIXED_SEED, 1024, (4, 6, 18), (1, 2, 3))
+    Av = np.concatenate([A_mix, np.full(8, 6, np.int32)]).astype(np.int32)
+    dv = np.concatenate([d_mix, np.full(8, 4, np.int32)]).astype(np.int32)
+    n = len(Av)
+    pos, st = W.roots(MIXED_SEED, n)
+    leaves = int((Av.astype(np.int64) ** dv).sum())
+    ctx = _setup(MIXED_SEED, n)
+    ctx.set_precision({"bf16": bcts.BF16, "fp8": bcts.FP8, "fp32": bcts.FP32}[args.precision])
+    dev = torch.device("cuda:0")
+    pos_t = torch.from_numpy(pos).to(dev)
+    st_t = torch.from_numpy(st).to(dev)
+    act_t = torch.zeros(n, dtype=torch.int32, device=dev)
+    q_t = torch.zeros(int(Av.sum()), dtype=torch.float32, device=dev)
+    corr = bcts.correction(True, C)
+    stream = torch.cuda.Stream()
+    tuned = None
+    if args.precision != "fp32":
+        with torch.cuda.stream(stream):
+            tuned = ctx.autotune(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, reps=2, stream=stream)
+        torch.cuda.synchronize()
+        print(f"# autotune mixed: {tuned}", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        # eager form (one launch sequence per step)
+        for _ in range(args.warmup):
+            ctx.search_batch_device(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, stream=stream)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.search_batch_device(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1) / args.steps
+        act_eager, q_eager = act_t.cpu().numpy().copy(), q_t.cpu().numpy().copy()
+        # graph form: capture once (warm-up replays), then time `steps` replays
+        ctx.search_batch_graph(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, replays=max(args.warmup, 1),
+                               stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.search_batch_graph(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, replays=args.steps, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
+    same = bool((act_t.cpu().numpy() == act_eager).all() and (q_t.cpu().numpy() == q_eager).all())
+    ctx.close()
+    out = {
+        "metric": "leaf evals/sec, mixed-shape batch (graph replay)", "value": leaves / (graph_ms * 1e-3),
+        "unit": "leaf evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8_e4m3", "fp32": "f32"}[args.precision],
+        "data": "synthetic (seeded sprite world, random Kaiming-uniform Nature-DQN)",
+        "config": {"workload": "1024 roots, A ~ U{4,6,18}, depth ~ U{1,2,3} + 8 roots A=6 depth 4, gamma 0.99, "
+                               "BCTS c=1.0, one captured HIP graph per step", "roots": n,
+                   "leaves_per_step": leaves, "precision": args.precision},
+        "eager_ms_per_step": eager_ms, "eager_value": leaves / (eager_ms * 1e-3),
+        "graph_equals_eager": same, "autotuned": tuned,
+    }
+    print(json.dumps(out))
+
+
+def _serve_once(args, budget, duration, warm, rate):
+    """Replay the Poisson request stream in real time; returns latency and
+    throughput figures over the requests that arrive after `warm` seconds."""
+    import numpy as np
+    from paper_2107_01715_amd import bcts, workload as W
+    t_arr, A_r, d_r = W.request_arrivals(SERVE_SEED, rate, duration)
+    n = len(t_arr)
+    pool = 4096                                 # distinct root states, cycled over the requests
+    pos, st = W.roots(SERVE_SEED, pool)
+    ctx = _setup(SERVE_SEED, pool, budget)
+    ctx.set_precision({"bf16": bcts.BF16, "fp8": bcts.FP8, "fp32": bcts.FP32}[args.precision])
+    corr = bcts.correction(True, C)
+    # warm the engine (allocations, first launches) before the clock starts
+    for i in range(8):
+        tk = ctx.submit(pos[i], st[i], int(d_r[i]), int(A_r[i]), GAMMA, corr)
+        while True:
+            ctx.progress()
+            r = ctx.poll(tk, int(A_r[i]))
+            if r is not None:
+                break
+    lat = np.full(n, np.nan)
+    pending = {}
+    i = 0
+    t0 = time.monotonic()
+    max_pending = 0
+    while i < n or pending:
+        now = time.monotonic() - t0
+        while i < n and t_arr[i] <= now:
+            k = i % pool
+            tk = ctx.submit(pos[k], st[k], int(d_r[i]), int(A_r[i]), GAMMA, corr)
+            pending[tk] = i
+            i += 1
+        left = ctx.progress()                   # requests queued or on the GPU
+        max_pending = max(max_pending, len(pending))
+        if left < len(pending):                 # some finished: collect them
+            for tk in list(pending):
+                j = pending[tk]
+                r = ctx.poll(tk, int(A_r[j]))
+                if r is not None:
+                    lat[j] = r[2] - (t0 + t_arr[j])
+                    del pending[tk]
+    wall = time.monotonic() - t0
+    ctx.close()
+    sel = t_arr >= warm
+    lm = lat[sel] * 1e3
+    leaves = (A_r.astype(np.int64) ** d_r)
+    return {"requests": int(n), "measured_requests": int(sel.sum()), "wall_s": wall,
+            "p50_ms": float(np.percentile(lm, 50)), "p99_ms": float(np.percentile(lm, 99)),
+            "mean_ms": float(lm.mean()), "max_ms": float(lm.max()),
+            "requests_per_s": float(n / wall), "leaf_evals_per_s": float(leaves.sum() / wall),
+            "max_pending": int(max_pending),
+            "budget_bytes": budget if budget else "80% of free device memory"}
+
+
+def run_serve(args):
+    rate, duration, warm = 2000.0, args.serve_seconds, min(5.0, args.serve_seconds / 4)
+    main_run = _serve_once(args, 0, duration, warm, rate)
+    print(f"# serve (default budget): {main_run}", file=sys.stderr, flush=True)
+    small = _serve_once(args, 1 << 30, min(duration, 20.0), min(warm, 5.0), rate)
+    print(f"# serve (1 GB budget): {small}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "serving request latency p50/p99 (Poisson 2000 req/s)", "value": main_run["p99_ms"],
+        "unit": "ms (p99)", "n_gpus": 1, "steps": main_run["requests"], "warmup": 0,
+        "ms_per_step": main_run["mean_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8_e4m3", "fp32": "f32"}[args.precision],
+        "data": "synthetic (seeded sprite world, random Kaiming-uniform Nature-DQN)",
+        "config": {"workload": f"Poisson arrivals 2000 req/s for {duration:g} s; A ~ U{{4,6,18}}, depth 1-4 "
+                               "(p .50/.30/.15/.05, A=18 caps at 3); gamma 0.99, BCTS c=1.0; latency = completion "
+                               f"- arrival after a {warm:g} s warm-up", "precision": args.precision},
+        "serve": main_run, "serve_1gb_budget": small,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +256,8 @@ def main():
     ap.add_argument("--skip-fp32-single", action="store_true")
     ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
     ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--quick", action="store_true",
                     help="headline precision only (no comparison forms, no accuracy): for profiler runs")
     args = ap.parse_args()
@@ -101,6 +265,10 @@ def main():
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the search shards over roots "
               f"with no communication; see DESIGN.md for the multi-GPU layout)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "mixed":
+        return run_mixed(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     # CPU baseline first: the worker pool forks before the GPU is touched
     cpu, oracle_ref = (None, {})

@@ -179,10 +179,10 @@ def mixed_shapes(seed: int, n: int, a_choices=(4, 6, 18), d_choices=(1, 2, 3)):
     return a.astype(np.int32), d.astype(np.int32)
 
 
-def request_stream(seed: int, rate: float, duration: float, max_requests: int | None = None):
+def request_arrivals(seed: int, rate: float, duration: float, max_requests: int | None = None):
     """Poisson arrivals (exponential gaps -ln(1-u)/rate); A uniform on
     {4,6,18}; d in {1,2,3,4} with p = .50/.30/.15/.05; A = 18 caps d at 3.
-    Returns arrival times (s), A, d and the stream's root states."""
+    Returns arrival times (s), A and d."""
     n_cap = int(rate * duration * 1.5 + 64) if max_requests is None else max_requests
     gaps = -np.log1p(-uniform01(seed, "req.gap", n_cap)) / rate
     t = np.cumsum(gaps)
@@ -195,5 +195,11 @@ def request_stream(seed: int, rate: float, duration: float, max_requests: int | 
     u = uniform01(seed, "req.d", n)
     d = np.where(u < 0.50, 1, np.where(u < 0.80, 2, np.where(u < 0.95, 3, 4))).astype(np.int32)
     d = np.where((a == 18) & (d > 3), 3, d).astype(np.int32)
-    pos, stacks = roots(seed, n)
+    return t, a, d
+
+
+def request_stream(seed: int, rate: float, duration: float, max_requests: int | None = None):
+    """request_arrivals plus one root state per request (positions, stacks)."""
+    t, a, d = request_arrivals(seed, rate, duration, max_requests)
+    pos, stacks = roots(seed, len(t))
     return t, a, d, pos, stacks
