@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32"])
-    ap.add_argument("--cpu-sample", type=int, default=16, help="roots timed through the oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="roots timed through the oracle (0 = skip)")
     ap.add_argument("--skip-fp32-single", action="store_true")
     ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
     ap.add_argument("--retune", action="store_true")
