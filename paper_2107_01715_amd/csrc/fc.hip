@@ -3,8 +3,10 @@
 // out to the same (h, w, c) order), BF16 or OCP e4m3 operands, FP32
 // accumulate.  H [n][512] in the operand type feeds fc2.
 //
-// A workgroup of 8 wavefronts computes a 256 (stacks) x 128 (neurons) tile:
-// wave (wm, wn) owns 64 x 64, i.e. 4 x 4 MFMA 16x16x32 fragments.  The K
+// A workgroup of 8 wavefronts computes a 256 (stacks) x 256 (neurons) tile:
+// wave (wm, wn) owns 64 x 128, i.e. 4 x 8 MFMA 16x16x32 fragments, so one
+// LDS operand read feeds 4 or 8 MFMAs and each global byte feeds 256 output
+// columns (the L2 -> CU path, not the matrix cores, bounds smaller tiles).  The K
 // loop moves 64 K values per stage: the next stage's tiles are loaded from
 // HBM/L2 into registers while the current stage's MFMAs run, then written to
 // the other half of a double-buffered LDS, so one barrier separates stages.
@@ -22,9 +24,9 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 constexpr int kThreads = 512;
-constexpr int kBM = 256, kBN = 128, kBK = 64, kK = 3136;
+constexpr int kBM = 256, kBN = 256, kBK = 64, kK = 3136;
 constexpr int kStages = kK / kBK;                 // 49
-static_assert(512 / kBN == 4, "the workgroup mapping assumes 4 neuron tiles");
+static_assert(512 / kBN == 2, "the workgroup mapping assumes 2 neuron tiles");
 
 __device__ __forceinline__ void lds_barrier() {
   __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
@@ -73,15 +75,15 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
   __shared__ __attribute__((aligned(16))) unsigned char Bs[2][kBN * RS];
 
   // Workgroups are dealt to the 8 XCDs round-robin (XCD = id mod 8), each
-  // with its own L2.  The 4 neuron tiles of one stack tile go to the same
+  // with its own L2.  The 2 neuron tiles of one stack tile go to the same
   // XCD in consecutive slots, so its X tile is fetched from HBM once and
-  // read by the other three from that XCD's L2.  The grid is padded to a
+  // read by the other from that XCD's L2.  The grid is padded to a
   // multiple of 8 stack tiles; padding workgroups leave at once.
   const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
-  const long long mt = (long long)(slot >> 2) * 8 + xcd;
+  const long long mt = (long long)(slot >> 1) * 8 + xcd;
   if (mt * kBM >= n) return;
   const long long m0 = mt * kBM;
-  const int n0 = (slot & 3) * kBN;
+  const int n0 = (slot & 1) * kBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   const int wm = wave >> 1, wn = wave & 1;        // 4 x 2 waves
@@ -115,9 +117,9 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
   }
   uint4 ra[AU], rb[BU];
 
-  f32x4 acc[4][4];            // [neuron frag][stack frag]
+  f32x4 acc[8][4];            // [neuron frag][stack frag]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -129,18 +131,17 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
     if (st + 1 < kStages) FC1_GLOAD(st + 1);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      V wv[4], xv[4];
+      V xv[4];
       const int kb = (ks * 32 + 8 * g) * EB;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        wv[i] = *reinterpret_cast<const V*>(&Bs[buf][(wn * 64 + i * 16 + r16) * RS + kb]);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         xv[j] = *reinterpret_cast<const V*>(&As[buf][(wm * 64 + j * 16 + r16) * RS + kb]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 8; ++i) {
+        const V wv = *reinterpret_cast<const V*>(&Bs[buf][(wn * 128 + i * 16 + r16) * RS + kb]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv[i], xv[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
+      }
     }
     if (st + 1 < kStages) FC1_LSTORE(buf ^ 1);
     lds_barrier();
@@ -148,10 +149,10 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #undef FC1_GLOAD
 #undef FC1_LSTORE
 
-  // epilogue: lane holds neurons n0 + wn*64 + 16i + 4g + q of stack m0 + wm*64 + 16j + r16
+  // epilogue: lane holds neurons n0 + wn*128 + 16i + 4g + q of stack m0 + wm*64 + 16j + r16
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int nb = n0 + wn * 64 + 16 * i + 4 * g;
+  for (int i = 0; i < 8; ++i) {
+    const int nb = n0 + wn * 128 + 16 * i + 4 * g;
     const float b0 = bias[nb], b1 = bias[nb + 1], b2 = bias[nb + 2], b3 = bias[nb + 3];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
