@@ -171,6 +171,51 @@ def qnet_unblob(blob: np.ndarray) -> dict[str, np.ndarray]:
 
 
 # ---------------------------------------------------------------------------
+# learned forward model (a fully connected stand-in for a learned simulator)
+# ---------------------------------------------------------------------------
+MLP_STATE = 100
+
+
+def mlp_shapes(A: int):
+    """Layer shapes in the canonical blob order ([out][in] matrices): l1 takes
+    the state then the one-hot action; out has the 100 next-state units then
+    the reward unit; q is the A-action leaf head on the state."""
+    return (("l1.w", (100, MLP_STATE + A)), ("l1.b", (100,)),
+            ("l2.w", (100, 100)), ("l2.b", (100,)),
+            ("l3.w", (100, 100)), ("l3.b", (100,)),
+            ("out.w", (MLP_STATE + 1, 100)), ("out.b", (MLP_STATE + 1,)),
+            ("q.w", (A, MLP_STATE)), ("q.b", (A,)))
+
+
+def mlp_numel(A: int) -> int:
+    return sum(int(np.prod(s)) for _, s in mlp_shapes(A))
+
+
+def mlp_weights(seed: int, A: int) -> dict[str, np.ndarray]:
+    """Weights and biases uniform on +-1/sqrt(fan_in) (the default
+    initialisation of a fully connected layer), drawn in FP64 and rounded to
+    FP32; the streams are keyed by A so each action count is its own model."""
+    out = {}
+    shapes = mlp_shapes(A)
+    for name, shape in shapes:
+        layer = name.split(".")[0]
+        fan_in = dict(shapes)[layer + ".w"][1]
+        u = uniform01(seed, f"mlp{A}." + name, int(np.prod(shape)))
+        out[name] = ((2.0 * u - 1.0) / math.sqrt(fan_in)).astype(np.float32).reshape(shape)
+    return out
+
+
+def mlp_blob(weights: dict[str, np.ndarray], A: int) -> np.ndarray:
+    return np.concatenate([weights[n].reshape(-1) for n, _ in mlp_shapes(A)]).astype(np.float32)
+
+
+def mlp_states(seed: int, n: int) -> np.ndarray:
+    """n root states, FP32 [n][100], uniform on [-1, 1)."""
+    u = uniform01(seed, "mlp.state", n * MLP_STATE)
+    return (2.0 * u - 1.0).astype(np.float32).reshape(n, MLP_STATE)
+
+
+# ---------------------------------------------------------------------------
 # mixed batches and request streams
 # ---------------------------------------------------------------------------
 def mixed_shapes(seed: int, n: int, a_choices=(4, 6, 18), d_choices=(1, 2, 3)):
