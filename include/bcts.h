@@ -218,6 +218,35 @@ bcts_status bcts_serve_config(bcts_ctx* ctx, int32_t max_batch, int32_t max_infl
 /* Device bytes one request of (depth, A) reserves while admitted.         */
 size_t bcts_request_bytes(int32_t depth, int32_t A);
 
+/* ---- learned forward-model world (Sec. 4.1's runtime study) ------------- */
+/* The paper also times tree search over a deep network that mimics a learned
+ * forward model: three hidden layers of width 100 fed a 100-dimensional
+ * state and a one-hot action.  Here the model maps x = [s ; onehot(a)]
+ * through ReLU(l1), ReLU(l2), ReLU(l3) to a linear output of 101 units (the
+ * next state, then the reward), and a leaf state is valued by the linear head
+ * Q(s, .) = q.w s + q.b; the search and the BCTS correction (Eq. 1, 3, 6) are
+ * those of the sprite world.  FP32.
+ *
+ * bcts_set_mlp installs the model for A actions (2 <= A <= 18) from an fp32
+ * blob in the order l1.w[100][100+A] (inputs: state then one-hot action),
+ * l1.b[100], l2.w[100][100], l2.b[100], l3.w[100][100], l3.b[100],
+ * out.w[101][100], out.b[101], q.w[A][100], q.b[A] ([out][in] matrices);
+ * n_floats must equal that total.  The blob is copied.                      */
+bcts_status bcts_set_mlp(bcts_ctx* ctx, int32_t A, const float* blob, size_t n_floats);
+/* Search n_roots root states (fp32 [n][100], host) to `depth` (0..16), every
+ * root with the model's A; out_action int32 [n], out_q fp32 [n][A] (the
+ * corrected root vector; Q0 at depth 0).  BCTS_E_STATE without a model,
+ * BCTS_E_INVAL on bad arguments or non-finite states, BCTS_E_NOMEM when the
+ * tree (A^k states per root for k < depth, plus one float per leaf) exceeds
+ * the budget.                                                              */
+bcts_status bcts_mlp_search(bcts_ctx* ctx, int32_t n_roots, const float* states, int32_t depth,
+                            float gamma, bcts_correction corr, int32_t* out_action, float* out_q);
+/* The same with device pointers (states, outputs), enqueued on hip_stream
+ * (NULL: the context's stream); nothing is copied and nothing synchronises.  */
+bcts_status bcts_mlp_search_device(bcts_ctx* ctx, int32_t n_roots, const float* d_states, int32_t depth,
+                                   float gamma, bcts_correction corr, int32_t* d_out_action,
+                                   float* d_out_q, void* hip_stream);
+
 /* ---- parity / debug exports (not on the timed path) -------------------- */
 /* Expand one root to `depth` and copy every node out in the index order of
  * Alg. 1 (level 1 first; node j*A + a is child a of node j).  Host outputs

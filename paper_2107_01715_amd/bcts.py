@@ -40,6 +40,7 @@ EXPORTS = (
     "bcts_submit", "bcts_progress", "bcts_poll", "bcts_serve_config", "bcts_request_bytes",
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
+    "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK = 0, 1, 2, 3
 
@@ -95,6 +96,11 @@ _set_tuning = _sig("bcts_set_tuning", c_int32, _P, c_int32, ctypes.c_int64)
 _get_tuning = _sig("bcts_get_tuning", c_int32, _P, c_int32, POINTER(ctypes.c_int64))
 _autotune = _sig("bcts_autotune", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, CorrectionC, _P, _P, c_int32, _P,
                  POINTER(ctypes.c_int64))
+
+_set_mlp = _sig("bcts_set_mlp", c_int32, _P, c_int32, _P, c_size_t)
+_mlp_search = _sig("bcts_mlp_search", c_int32, _P, c_int32, _P, c_int32, c_float, CorrectionC, _P, _P)
+_mlp_search_device = _sig("bcts_mlp_search_device", c_int32, _P, c_int32, _P, c_int32, c_float, CorrectionC, _P, _P,
+                          _P)
 
 
 def _ptr(a: np.ndarray):
@@ -251,6 +257,28 @@ def bcts_serve_config(ctx, max_batch: int, max_inflight: int):
 
 def bcts_request_bytes(depth: int, A: int) -> int:
     return int(_request_bytes(depth, A))
+
+
+def bcts_set_mlp(ctx, A: int, blob):
+    b = _arr(blob, np.float32)
+    _check(ctx, _set_mlp(ctx, A, _ptr(b), b.size))
+
+
+def bcts_mlp_search(ctx, states, depth: int, A: int, gamma: float, corr: CorrectionC):
+    """(actions int32 [n], q float32 [n][A]) for host states [n][100]; A is
+    the model's action count (sizes the output)."""
+    st = _arr(states, np.float32)
+    n = st.shape[0]
+    act = np.zeros(n, np.int32)
+    q = np.zeros((n, A), np.float32)
+    _check(ctx, _mlp_search(ctx, n, _ptr(st), depth, gamma, corr, _ptr(act), _ptr(q)))
+    return act, q
+
+
+def bcts_mlp_search_device(ctx, states_t, depth: int, gamma: float, corr: CorrectionC, act_t, q_t, stream=None):
+    s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(ctx, _mlp_search_device(ctx, states_t.shape[0], _dev(states_t, torch.float32), depth, gamma, corr,
+                                   _dev(act_t, torch.int32), _dev(q_t, torch.float32), s))
 
 
 def bcts_debug_expand(ctx, pos, stack, depth: int, A: int):

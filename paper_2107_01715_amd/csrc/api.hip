@@ -135,6 +135,10 @@ struct bcts_ctx {
   double t_ms[24] = {0};
   // serving
   struct ServeEngine* serve = nullptr;
+  // learned forward-model world
+  void* mlp_mem = nullptr;
+  MlpDev mlp{};
+  bool mlp_set = false;
 };
 
 namespace {
@@ -815,6 +819,7 @@ void bcts_destroy(bcts_ctx* c) {
   delete c->serve;
   if (c->arena) (void)hipFree(c->arena);
   if (c->wmem) (void)hipFree(c->wmem);
+  if (c->mlp_mem) (void)hipFree(c->mlp_mem);
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -1386,6 +1391,182 @@ bcts_status bcts_set_timing(bcts_ctx* c, int32_t enabled) {
 bcts_status bcts_get_timing(bcts_ctx* c, double* out24) {
   if (!c || !out24) return BCTS_E_INVAL;
   for (int i = 0; i < 24; ++i) out24[i] = c->t_ms[i];
+  return BCTS_OK;
+}
+
+// ---- learned forward-model world (Sec. 4.1) --------------------------------
+
+namespace {
+constexpr int kMlpMaxD = 16;
+
+size_t mlp_numel(int A) {
+  return (size_t)100 * (100 + A) + 100 + 100 * 100 + 100 + 100 * 100 + 100 + 101 * 100 + 101 + (size_t)A * 100 + A;
+}
+
+// arena layout of one forward-model search (byte offsets)
+struct MlpPlan {
+  size_t states[kMlpMaxD + 1] = {0}, ret[kMlpMaxD + 1] = {0};   // levels 1..d-1 (ret also at level 1)
+  size_t v1 = 0, leaf = 0, qd = 0, in_states = 0, out_act = 0, out_q = 0, total = 0;
+};
+
+bcts_status mlp_plan(bcts_ctx* c, int n, int d, bool host_io, MlpPlan& p) {
+  const int A = c->mlp.A;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
+  long long cnt = n;
+  for (int k = 1; k <= d; ++k) {
+    if (cnt > (1LL << 40) / A) return fail(c, BCTS_E_INVAL, "tree too large: %d roots, A=%d, depth %d", n, A, d);
+    cnt *= A;
+    if (k < d) p.states[k] = take(sizeof(float) * 100 * (size_t)cnt);
+    if (k < d || k == 1) p.ret[k] = take(sizeof(float) * (size_t)cnt);
+  }
+  if (d >= 1) {
+    p.v1 = take(sizeof(float) * (size_t)n * A);
+    p.leaf = take(sizeof(float) * (size_t)cnt);
+    p.qd = take(sizeof(float) * (size_t)n * A);
+  }
+  if (host_io) {
+    p.in_states = take(sizeof(float) * 100 * (size_t)n);
+    p.out_act = take(sizeof(int32_t) * (size_t)n);
+    p.out_q = take(sizeof(float) * (size_t)n * A);
+  }
+  p.total = o;
+  return BCTS_OK;
+}
+
+bcts_status mlp_validate(bcts_ctx* c, int n, int d, float gamma, const bcts_correction& corr) {
+  if (n <= 0) return fail(c, BCTS_E_INVAL, "n_roots=%d must be positive", n);
+  if (d < 0 || d > kMlpMaxD) return fail(c, BCTS_E_INVAL, "depth=%d outside [0,%d]", d, kMlpMaxD);
+  if (!(gamma > 0.f && gamma <= 1.f)) return fail(c, BCTS_E_INVAL, "gamma=%g outside (0,1]", gamma);
+  if (corr.enabled && !std::isfinite(corr.scale)) return fail(c, BCTS_E_INVAL, "correction scale is not finite");
+  if (corr.enabled && corr.mode != BCTS_CORR_EQ6 && corr.mode != BCTS_CORR_EXACT_GEV)
+    return fail(c, BCTS_E_INVAL, "unknown correction mode %d", corr.mode);
+  if (!c->mlp_set) return fail(c, BCTS_E_STATE, "no forward model set (bcts_set_mlp)");
+  return BCTS_OK;
+}
+
+// Enqueue one forward-model search on stream s: level by level, children of
+// level k from the states of level k - 1; the leaf level writes
+// return + gamma^d max Q, reduced per (root, root action); then the root
+// values and the correction.
+void mlp_enqueue(bcts_ctx* c, const MlpPlan& p, int n, int d, const float* states, float gamma,
+                 const bcts_correction& corr, int32_t* act, float* q, hipStream_t s) {
+  const int A = c->mlp.A;
+  char* base = c->arena;
+  auto F = [&](size_t off) { return reinterpret_cast<float*>(base + off); };
+  const bool corr_on = corr.enabled && d >= 1;
+  const float gamma_d = (float)std::pow((double)gamma, d);
+  long long cnt = n;
+  for (int k = 1; k <= d; ++k) {
+    cnt *= A;
+    const float* ps = k == 1 ? states : F(p.states[k - 1]);
+    const float* pret = k == 1 ? nullptr : F(p.ret[k - 1]);
+    float* os = k < d ? F(p.states[k]) : nullptr;
+    float* oret = (k < d || k == 1) ? F(p.ret[k]) : nullptr;
+    float* ov = (k == 1 && corr_on) ? F(p.v1) : nullptr;
+    float* oleaf = k == d ? F(p.leaf) : nullptr;
+    launch_mlp_level(c->mlp, cnt, ps, pret, (float)std::pow((double)gamma, k - 1), os, oret, ov, oleaf, gamma_d, s);
+  }
+  if (d >= 1) launch_mlp_blockmax((long long)n * A, cnt / ((long long)n * A), F(p.leaf), F(p.qd), s);
+  double pe = 0.0, po = 0.0;
+  if (corr_on) {
+    if (corr.mode == BCTS_CORR_EXACT_GEV) gev_coeffs(A, d, &pe, &po);
+    else eq6_coeffs(A, d, &pe, &po);
+  }
+  launch_mlp_root(c->mlp, n, d, states, d >= 1 ? F(p.ret[1]) : nullptr, corr_on ? F(p.v1) : nullptr,
+                  d >= 1 ? F(p.qd) : nullptr, gamma, gamma_d, (float)pe, (float)po, corr_on ? 1 : 0,
+                  corr.enabled ? corr.scale : 0.f, act, q, s);
+}
+}  // namespace
+
+bcts_status bcts_set_mlp(bcts_ctx* c, int32_t A, const float* blob, size_t n_floats) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (A < 2 || A > kMaxA) return fail(c, BCTS_E_INVAL, "A=%d outside [2,18]", A);
+  if (!blob) return fail(c, BCTS_E_INVAL, "blob is NULL");
+  if (n_floats != mlp_numel(A))
+    return fail(c, BCTS_E_INVAL, "blob has %zu floats, expected %zu for A=%d", n_floats, mlp_numel(A), A);
+  for (size_t i = 0; i < n_floats; ++i)
+    if (!std::isfinite(blob[i])) return fail(c, BCTS_E_INVAL, "blob[%zu] is not finite", i);
+  HIPCHECK(c, hipSetDevice(c->device));
+  // device order: w1s [100][100], w1a [A][100], b1, w2, b2, w3, b3, wo [101][100], bo, wq [A][100], bq
+  const float* l1w = blob;
+  const float* rest = blob + (size_t)100 * (100 + A);   // l1.b onwards, already in device order after w1a
+  std::vector<float> h;
+  h.reserve(n_floats);
+  for (int o = 0; o < 100; ++o)
+    for (int k = 0; k < 100; ++k) h.push_back(l1w[(size_t)o * (100 + A) + k]);
+  for (int a = 0; a < A; ++a)
+    for (int o = 0; o < 100; ++o) h.push_back(l1w[(size_t)o * (100 + A) + 100 + a]);
+  h.insert(h.end(), rest, blob + n_floats);
+  if (c->mlp_mem) {
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipFree(c->mlp_mem));
+    c->mlp_mem = nullptr;
+    c->mlp_set = false;
+  }
+  HIPCHECK(c, hipMalloc(&c->mlp_mem, sizeof(float) * h.size()));
+  HIPCHECK(c, hipMemcpy(c->mlp_mem, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+  const float* d0 = static_cast<const float*>(c->mlp_mem);
+  size_t o = 0;
+  auto next = [&](size_t k) { const float* p = d0 + o; o += k; return p; };
+  MlpDev m;
+  m.A = A;
+  m.w1s = next(100 * 100);
+  m.w1a = next((size_t)A * 100);
+  m.b1 = next(100);
+  m.w2 = next(100 * 100);
+  m.b2 = next(100);
+  m.w3 = next(100 * 100);
+  m.b3 = next(100);
+  m.wo = next(101 * 100);
+  m.bo = next(101);
+  m.wq = next((size_t)A * 100);
+  m.bq = next(A);
+  c->mlp = m;
+  c->mlp_set = true;
+  return BCTS_OK;
+}
+
+bcts_status bcts_mlp_search_device(bcts_ctx* c, int32_t n_roots, const float* d_states, int32_t depth, float gamma,
+                                   bcts_correction corr, int32_t* d_out_action, float* d_out_q, void* hip_stream) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = mlp_validate(c, n_roots, depth, gamma, corr)) != BCTS_OK) return st;
+  if (!d_states || !d_out_action || !d_out_q) return fail(c, BCTS_E_INVAL, "NULL pointer");
+  HIPCHECK(c, hipSetDevice(c->device));
+  MlpPlan p;
+  if ((st = mlp_plan(c, n_roots, depth, false, p)) != BCTS_OK) return st;
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+  mlp_enqueue(c, p, n_roots, depth, d_states, gamma, corr, d_out_action, d_out_q, s);
+  HIPCHECK(c, hipGetLastError());
+  return BCTS_OK;
+}
+
+bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, int32_t depth, float gamma,
+                            bcts_correction corr, int32_t* out_action, float* out_q) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = mlp_validate(c, n_roots, depth, gamma, corr)) != BCTS_OK) return st;
+  if (!states || !out_action || !out_q) return fail(c, BCTS_E_INVAL, "NULL pointer");
+  for (long long i = 0; i < (long long)n_roots * 100; ++i)
+    if (!std::isfinite(states[i])) return fail(c, BCTS_E_INVAL, "state value %lld is not finite", i);
+  HIPCHECK(c, hipSetDevice(c->device));
+  MlpPlan p;
+  if ((st = mlp_plan(c, n_roots, depth, true, p)) != BCTS_OK) return st;
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  const int A = c->mlp.A;
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.in_states, states, sizeof(float) * 100 * (size_t)n_roots,
+                             hipMemcpyHostToDevice, c->stream));
+  int32_t* d_act = reinterpret_cast<int32_t*>(c->arena + p.out_act);
+  float* d_q = reinterpret_cast<float*>(c->arena + p.out_q);
+  mlp_enqueue(c, p, n_roots, depth, reinterpret_cast<const float*>(c->arena + p.in_states), gamma, corr, d_act, d_q,
+              c->stream);
+  HIPCHECK(c, hipGetLastError());
+  HIPCHECK(c, hipMemcpyAsync(out_action, d_act, sizeof(int32_t) * (size_t)n_roots, hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(out_q, d_q, sizeof(float) * (size_t)n_roots * A, hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
   return BCTS_OK;
 }
 

@@ -114,6 +114,20 @@ struct QnetDev {
   const void* wf8[5];          // e4m3
 };
 
+// Learned forward-model world: weights on the device, FP32, [out][in] rows of
+// 100 inputs.  l1's state part and its one-hot action columns are split so
+// that an action adds one column: w1a[a][o] = l1.w[o][100 + a].
+struct MlpDev {
+  int A;
+  const float *w1s, *w1a, *b1, *w2, *b2, *w3, *b3, *wo, *bo, *wq, *bq;
+};
+void launch_mlp_level(const MlpDev& m, long long n, const float* ps, const float* pret, float gpow, float* os,
+                      float* oret, float* ov, float* oleaf, float gamma_d, hipStream_t s);
+void launch_mlp_blockmax(long long n_blocks, long long block, const float* leaf, float* qd, hipStream_t s);
+void launch_mlp_root(const MlpDev& m, int n, int d, const float* states, const float* ret1, const float* v1,
+                     const float* qd, float gamma, float gamma_d, float pen_e, float pen_o, int corr, float scale,
+                     int32_t* act, float* q, hipStream_t s);
+
 // Copies W[N][K] (element size eb bytes) into fragment-major order.
 void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hipStream_t s);
 
