@@ -24,10 +24,15 @@ Two further workloads print their own JSON line:
   --workload serve  Poisson arrivals at 2000 requests/s for 60 s (A in
                     {4,6,18}, depth 1-4), BF16, continuous batching through
                     submit/progress/poll; p50/p99 request latency after a
-                    5 s warm-up, plus a run under a 1 GB device budget.
+                    5 s warm-up, plus a run under a 1 GB device budget;
+  --workload mlp    the learned forward-model world (a fully connected
+                    model with three hidden layers of width 100, A = 2 and
+                    10): GPU time per search of one root against depth, the
+                    FP64 oracle's depth-first search on the host beside it,
+                    and the batched throughput of 64 roots.
 
     python bench.py [--steps K] [--warmup W] [--precision bf16|fp8|fp32]
-                    [--workload headline|mixed|serve]
+                    [--workload headline|mixed|serve|mlp]
 """
 from __future__ import annotations
 
@@ -50,7 +55,7 @@ LAYER_FLOPS = {"conv1": 2 * 400 * 32 * 256, "conv2": 2 * 81 * 64 * 512, "conv3":
                "fc1": 2 * 512 * 3136, "fc2": 2 * A * 512}
 LAYER_KERNEL = {"conv1": "layer_kernel<0,P>", "conv2": "layer_kernel<1,P>", "conv3": "layer_kernel<2,P>",
                 "fc1": "fc1_kernel<P>", "fc2": "layer_kernel<4,P>", "conv_fused": "conv_fused_kernel<P,T>"}
-MIXED_SEED, SERVE_SEED = 1004, 1005
+MIXED_SEED, SERVE_SEED, MLP_SEED = 1004, 1005, 1007
 # algorithmic bytes per new node written by the expansion: frame, positions, return, reward
 EXPAND_BYTES_PER_NODE = 7056 + 16 + 4 + 1
 
@@ -246,6 +251,91 @@ def run_serve(args):
     print(json.dumps(out))
 
 
+def _oracle_mlp_time(A, d, budget_s):
+    """Host time of one depth-first search of the FP64 oracle (one root),
+    averaged over as many roots as fit the budget (at least one)."""
+    import numpy as np
+    from paper_2107_01715_amd import workload as W
+    from oracle import mlp as M
+    w = M.prepare(W.mlp_weights(WEIGHT_SEED, A))
+    st = W.mlp_states(MLP_SEED, 16).astype(np.float64)
+    t0, k = time.perf_counter(), 0
+    while True:
+        M.search(w, st[k % 16], d, A, GAMMA, correction=True, c=C)
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k >= 16:
+            break
+    return (time.perf_counter() - t0) / k, k
+
+
+def run_mlp(args):
+    """Forward-model world: time per search (one root, as one action
+    selection) against depth on the GPU, with the oracle's DFS on the host
+    beside it for the depths it finishes, and the batched throughput."""
+    import numpy as np
+    import torch
+    from paper_2107_01715_amd import bcts, workload as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    corr = bcts.correction(True, C)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows, batched = [], {}
+    cpu_rows = []
+    for A, dmax in ((2, 14), (10, 6)):
+        ctx = bcts.Context(0)
+        ctx.set_mlp(A, W.mlp_blob(W.mlp_weights(WEIGHT_SEED, A), A))
+        st = torch.from_numpy(W.mlp_states(MLP_SEED, 64)).to(dev)
+        act = torch.zeros(64, dtype=torch.int32, device=dev)
+        q = torch.zeros(64, A, dtype=torch.float32, device=dev)
+        with torch.cuda.stream(stream):
+            for d in range(1, dmax + 1):
+                reps = 50 if A ** d < 10 ** 5 else 10
+                for _ in range(3):
+                    ctx.mlp_search_device(st[:1], d, GAMMA, corr, act[:1], q[:1], stream=stream)
+                e0.record(stream)
+                for i in range(reps):
+                    ctx.mlp_search_device(st[i % 64:i % 64 + 1], d, GAMMA, corr, act[:1], q[:1], stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                rows.append({"A": A, "depth": d, "leaves": A ** d, "gpu_ms_per_search": ms,
+                             "gpu_leaf_evals_per_s": A ** d / (ms * 1e-3)})
+            # batched: 64 roots at the deepest depth
+            d = dmax - 1 if A == 10 else dmax
+            for _ in range(2):
+                ctx.mlp_search_device(st, d, GAMMA, corr, act, q, stream=stream)
+            e0.record(stream)
+            for _ in range(args.steps):
+                ctx.mlp_search_device(st, d, GAMMA, corr, act, q, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            batched[A] = {"roots": 64, "depth": d, "leaves": 64 * A ** d, "ms_per_step": ms,
+                          "leaf_evals_per_s": 64 * A ** d / (ms * 1e-3)}
+        ctx.close()
+        print(f"# mlp A={A}: {[(r['depth'], round(r['gpu_ms_per_search'], 4)) for r in rows if r['A'] == A]}",
+              file=sys.stderr, flush=True)
+    if args.cpu_sample > 0:
+        for A, dmax in ((2, 10), (10, 4)):
+            for d in range(1, dmax + 1):
+                sec, k = _oracle_mlp_time(A, d, 2.0)
+                cpu_rows.append({"A": A, "depth": d, "oracle_dfs_ms_per_search": sec * 1e3, "roots_timed": k})
+    head = batched[10]
+    out = {
+        "metric": "leaf evals/sec, learned forward-model world (A=10, 64 roots)", "value": head["leaf_evals_per_s"],
+        "unit": "leaf evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (random fully connected forward model, uniform +-1/sqrt(fan_in))",
+        "config": {"workload": f"64 root states, A=10, depth {head['depth']}, gamma 0.99, BCTS c=1.0; per-search "
+                               "times: one root per search, A in {2, 10}, depth 1..14 / 1..6"},
+        "batched": batched, "per_search": rows,
+        "cpu_baseline": {"kind": "oracle", "cores": 1, "rows": cpu_rows,
+                         "sample": "FP64 depth-first search of one root on one host core, averaged over up to "
+                                   "16 roots within 2 s per depth"} if cpu_rows else None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,7 +346,7 @@ def main():
     ap.add_argument("--skip-fp32-single", action="store_true")
     ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
     ap.add_argument("--retune", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--quick", action="store_true",
                     help="headline precision only (no comparison forms, no accuracy): for profiler runs")
@@ -269,6 +359,8 @@ def main():
         return run_mixed(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "mlp":
+        return run_mlp(args)
 
     # CPU baseline first: the worker pool forks before the GPU is touched
     cpu, oracle_ref = (None, {})

@@ -12,8 +12,8 @@
 // FP32 throughout.  On CDNA4 the FP32 matrix cores have the same peak as the
 // FP32 vector units (157.3 TFLOP/s), and at width 100 the work per child is
 // small next to its state traffic, so the layers run as register-tiled FMA
-// loops: a workgroup takes 64 children, keeps their activations in LDS and
-// each thread owns one output unit of 32 children.  Every sum runs in a fixed
+// loops: a workgroup takes 64 children (8 on small levels), keeps their
+// activations in LDS and each thread owns one output unit of 32 (4) children.  Every sum runs in a fixed
 // order (bias, the action column, then k = 0..99), so results do not depend
 // on batching.
 #include "bcts_internal.h"
@@ -22,33 +22,54 @@ namespace bcts {
 namespace {
 
 constexpr int kS = 100;          // state / hidden width
-constexpr int kMT = 64;          // children per tile
+constexpr int kMT = 64;          // children per tile (large levels)
+constexpr int kMTs = 8;          // children per tile (small levels)
 constexpr int kXS = 104;         // LDS row stride in floats (16-byte aligned rows)
 constexpr int kThreads = 256;
 
-// Y[r][col] for this thread's 32 rows: bias[col] (+ extra[r]) + sum_k W[col][k] X[r][k]
-template <bool RELU>
+// Y[r][col] for this thread's R rows: bias[col] (+ extra[r]) + sum_k W[col][k] X[r][k].
+// Large tiles (R = 32) read their weight row one float4 per K step; small
+// tiles (R <= 8, used when a level has few children and a lone tile is
+// latency-bound) request the whole row at once into registers.
+template <bool RELU, int R>
 __device__ __forceinline__ void dense(const float* __restrict__ W, const float* __restrict__ bias, int nout,
                                       const float* X, float* Y, int col, int rh, const float* extra) {
   if (col < nout) {
-    float acc[32];
+    float acc[R];
     const float b = bias[col];
 #pragma unroll
-    for (int r = 0; r < 32; ++r) acc[r] = b + (extra ? extra[r] : 0.f);
+    for (int r = 0; r < R; ++r) acc[r] = b + (extra ? extra[r] : 0.f);
     const float4* wr = reinterpret_cast<const float4*>(W + (size_t)col * kS);
-    for (int k4 = 0; k4 < kS / 4; ++k4) {
-      const float4 w = wr[k4];
+    if constexpr (R <= 8) {
+      float4 wv[kS / 4];
 #pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        const float4 x = *reinterpret_cast<const float4*>(X + (rh * 32 + r) * kXS + 4 * k4);
-        acc[r] = fmaf(w.x, x.x, acc[r]);
-        acc[r] = fmaf(w.y, x.y, acc[r]);
-        acc[r] = fmaf(w.z, x.z, acc[r]);
-        acc[r] = fmaf(w.w, x.w, acc[r]);
+      for (int k4 = 0; k4 < kS / 4; ++k4) wv[k4] = wr[k4];
+#pragma unroll
+      for (int k4 = 0; k4 < kS / 4; ++k4) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float4 x = *reinterpret_cast<const float4*>(X + (rh * R + r) * kXS + 4 * k4);
+          acc[r] = fmaf(wv[k4].x, x.x, acc[r]);
+          acc[r] = fmaf(wv[k4].y, x.y, acc[r]);
+          acc[r] = fmaf(wv[k4].z, x.z, acc[r]);
+          acc[r] = fmaf(wv[k4].w, x.w, acc[r]);
+        }
+      }
+    } else {
+      for (int k4 = 0; k4 < kS / 4; ++k4) {
+        const float4 w = wr[k4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float4 x = *reinterpret_cast<const float4*>(X + (rh * R + r) * kXS + 4 * k4);
+          acc[r] = fmaf(w.x, x.x, acc[r]);
+          acc[r] = fmaf(w.y, x.y, acc[r]);
+          acc[r] = fmaf(w.z, x.z, acc[r]);
+          acc[r] = fmaf(w.w, x.w, acc[r]);
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 32; ++r) Y[(rh * 32 + r) * kXS + col] = RELU ? fmaxf(acc[r], 0.f) : acc[r];
+    for (int r = 0; r < R; ++r) Y[(rh * R + r) * kXS + col] = RELU ? fmaxf(acc[r], 0.f) : acc[r];
   }
 }
 
@@ -59,20 +80,22 @@ __device__ __forceinline__ void dense(const float* __restrict__ W, const float* 
 //   os    child states (null: not kept), oret child returns (null: not kept)
 //   ov    max_a Q(child, a) (null: not needed)
 //   oleaf return + gamma^d max_a Q (null: not a leaf level)
+template <int MT>
 __global__ void __launch_bounds__(kThreads) mlp_level_kernel(MlpDev m, long long n, const float* __restrict__ ps,
                                                              const float* __restrict__ pret, float gpow,
                                                              float* __restrict__ os, float* __restrict__ oret,
                                                              float* __restrict__ ov, float* __restrict__ oleaf,
                                                              float gamma_d) {
-  __shared__ __attribute__((aligned(16))) float xa[kMT * kXS];
-  __shared__ __attribute__((aligned(16))) float xb[kMT * kXS];
-  __shared__ float rwd[kMT];
+  constexpr int R = MT / 2;                    // rows per thread: 2 row halves x 128 units
+  __shared__ __attribute__((aligned(16))) float xa[MT * kXS];
+  __shared__ __attribute__((aligned(16))) float xb[MT * kXS];
+  __shared__ float rwd[MT];
   const int tid = threadIdx.x, col = tid & 127, rh = tid >> 7;
   const int A = m.A;
   const bool head = ov || oleaf;
-  for (long long c0 = (long long)blockIdx.x * kMT; c0 < n; c0 += (long long)gridDim.x * kMT) {
+  for (long long c0 = (long long)blockIdx.x * MT; c0 < n; c0 += (long long)gridDim.x * MT) {
     // parent states; rows past n repeat the last child (computed, never stored)
-    for (int e = tid; e < kMT * (kS / 4); e += kThreads) {
+    for (int e = tid; e < MT * (kS / 4); e += kThreads) {
       const int row = e / (kS / 4), q = e % (kS / 4);
       const long long c = (c0 + row < n) ? c0 + row : n - 1;
       const float4 v = reinterpret_cast<const float4*>(ps + (c / A) * kS)[q];
@@ -81,35 +104,35 @@ __global__ void __launch_bounds__(kThreads) mlp_level_kernel(MlpDev m, long long
     __syncthreads();
     // layer 1: the one-hot action selects one column of l1.w
     {
-      float extra[32];
+      float extra[R];
 #pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        long long c = c0 + rh * 32 + r;
+      for (int r = 0; r < R; ++r) {
+        long long c = c0 + rh * R + r;
         if (c >= n) c = n - 1;
         extra[r] = col < kS ? m.w1a[(size_t)(c % A) * kS + col] : 0.f;
       }
-      dense<true>(m.w1s, m.b1, kS, xa, xb, col, rh, extra);
+      dense<true, R>(m.w1s, m.b1, kS, xa, xb, col, rh, extra);
     }
     __syncthreads();
-    dense<true>(m.w2, m.b2, kS, xb, xa, col, rh, nullptr);
+    dense<true, R>(m.w2, m.b2, kS, xb, xa, col, rh, nullptr);
     __syncthreads();
-    dense<true>(m.w3, m.b3, kS, xa, xb, col, rh, nullptr);
+    dense<true, R>(m.w3, m.b3, kS, xa, xb, col, rh, nullptr);
     __syncthreads();
-    dense<false>(m.wo, m.bo, kS + 1, xb, xa, col, rh, nullptr);   // units 0..99 next state, 100 reward
+    dense<false, R>(m.wo, m.bo, kS + 1, xb, xa, col, rh, nullptr);   // units 0..99 next state, 100 reward
     __syncthreads();
-    if (tid < kMT) rwd[tid] = xa[tid * kXS + kS];
+    if (tid < MT) rwd[tid] = xa[tid * kXS + kS];
     __syncthreads();
     // returns and states
-    if (tid < kMT && c0 + tid < n) {
+    if (tid < MT && c0 + tid < n) {
       const long long c = c0 + tid;
       const float r = fmaf(gpow, rwd[tid], pret ? pret[c / A] : 0.f);
       rwd[tid] = r;                           // now the child's return
       if (oret) oret[c] = r;
-    } else if (tid < kMT) {
+    } else if (tid < MT) {
       rwd[tid] = 0.f;
     }
     if (os)
-      for (int e = tid; e < kMT * (kS / 4); e += kThreads) {
+      for (int e = tid; e < MT * (kS / 4); e += kThreads) {
         const int row = e / (kS / 4), q = e % (kS / 4);
         if (c0 + row < n)
           reinterpret_cast<float4*>(os + (c0 + row) * kS)[q] = *reinterpret_cast<const float4*>(&xa[row * kXS + 4 * q]);
@@ -117,7 +140,7 @@ __global__ void __launch_bounds__(kThreads) mlp_level_kernel(MlpDev m, long long
     __syncthreads();
     // leaf head: 4 lanes per child, actions a = part, part + 4, ...
     if (head) {
-      const int row = tid >> 2, part = tid & 3;
+      const int row = (tid >> 2) < MT ? (tid >> 2) : MT - 1, part = tid & 3;
       float vmax = -INFINITY;
       for (int a = part; a < A; a += 4) {
         float acc = m.bq[a];
@@ -134,7 +157,7 @@ __global__ void __launch_bounds__(kThreads) mlp_level_kernel(MlpDev m, long long
       }
       vmax = fmaxf(vmax, __shfl_xor(vmax, 1));
       vmax = fmaxf(vmax, __shfl_xor(vmax, 2));
-      if (part == 0 && c0 + row < n) {
+      if (part == 0 && (tid >> 2) < MT && c0 + row < n) {
         const long long c = c0 + row;
         if (ov) ov[c] = vmax;
         if (oleaf) oleaf[c] = fmaf(gamma_d, vmax, rwd[row]);
@@ -215,10 +238,18 @@ __global__ void __launch_bounds__(64) mlp_root_kernel(MlpDev m, int d, const flo
 void launch_mlp_level(const MlpDev& m, long long n, const float* ps, const float* pret, float gpow, float* os,
                       float* oret, float* ov, float* oleaf, float gamma_d, hipStream_t s) {
   if (n <= 0) return;
+  // a level with fewer than ~2 large tiles per CU runs in small tiles: more
+  // workgroups, 4 rows per thread, weights requested at once
+  if (n < 2LL * 256 * kMT) {
+    const long long tiles = (n + kMTs - 1) / kMTs;
+    hipLaunchKernelGGL(mlp_level_kernel<kMTs>, dim3((unsigned)tiles), dim3(kThreads), 0, s, m, n, ps, pret, gpow,
+                       os, oret, ov, oleaf, gamma_d);
+    return;
+  }
   const long long tiles = (n + kMT - 1) / kMT;
   const unsigned grid = (unsigned)(tiles < 65536 ? tiles : 65536);
-  hipLaunchKernelGGL(mlp_level_kernel, dim3(grid), dim3(kThreads), 0, s, m, n, ps, pret, gpow, os, oret, ov, oleaf,
-                     gamma_d);
+  hipLaunchKernelGGL(mlp_level_kernel<kMT>, dim3(grid), dim3(kThreads), 0, s, m, n, ps, pret, gpow, os, oret, ov,
+                     oleaf, gamma_d);
 }
 
 void launch_mlp_blockmax(long long n_blocks, long long block, const float* leaf, float* qd, hipStream_t s) {
