@@ -171,3 +171,81 @@ def node_at(world: World, pos, stack, acts):
         p, s, r = E.step(p, s, a, world.delta, world.vel)
         rs.append(r)
     return p, s, rs
+
+
+def level_discounts_f32(gamma: float, d: int) -> list:
+    """The FP32 discount of each level's reward as the library forms it: the
+    host multiplies the FP32 gamma into a double level by level and rounds
+    each power to FP32 (gamma^(k-1) for level k)."""
+    g, gf, out = 1.0, float(np.float32(gamma)), []
+    for _ in range(d):
+        out.append(float(np.float32(g)))
+        g *= gf
+    return out
+
+
+def ret_step_f32(prev: float, gp: float, r: int) -> float:
+    """FP32 return of a child: fma(gp, r, prev) rounded once (the product of
+    an FP32 discount and a reward <= 7 and its sum with an FP32 return are
+    exact in FP64, so one rounding to FP32 is the fused multiply-add)."""
+    return float(np.float32(np.float64(prev) + np.float64(gp) * np.float64(r)))
+
+
+def search_beam(world: World, pos, stack, d: int, A: int, gamma: float, beam: int,
+                correction: bool = True, c: float = 1.0, mode: str = "eq6") -> Result:
+    """Pruned Batch-BFS: the paper leaves early pruning to future work and
+    only sketches it (an index array of unpruned states, updated at each
+    pruning step, then used to trace the root action, Sec. 4).  The rule read
+    here: the tree grows level by level as in Alg. 1; at every level
+    k = 2..d-1, inside each root action's sub-tree, only the `beam` nodes
+    with the largest discounted return so far are expanded further (ties:
+    lowest index; the ranking uses the library's FP32 returns, so both sides
+    take the same decision); the leaves are all children of the kept
+    level-(d-1) nodes.  Q_d(a0) is the max over a0's surviving leaves of
+    R + gamma^d max_a Q (FP64); the depth-0/1 quantities of the correction
+    are untouched.  beam = 0 is the exhaustive search."""
+    if beam == 0 or d <= 2:
+        return search(world, pos, stack, d, A, gamma, correction, c, mode)
+    gps = level_discounts_f32(gamma, d)
+    # a node: (a0, positions, stack, R64, R32); level 1 = the root's children
+    level = []
+    for a, (p1, s1, r) in enumerate(children(world, pos, stack, A)):
+        level.append((a, p1, s1, float(r), ret_step_f32(0.0, gps[0], r)))
+    for k in range(2, d + 1):
+        nxt = []
+        for (a0, pk, sk, R64, R32) in level:
+            for a, (p1, s1, r) in enumerate(children(world, pk, sk, A)):
+                nxt.append((a0, p1, s1, R64 + gamma ** (k - 1) * r, ret_step_f32(R32, gps[k - 1], r)))
+        if k <= d - 1:
+            kept = []
+            for a0 in range(A):
+                blk = [i for i, nd in enumerate(nxt) if nd[0] == a0]
+                if len(blk) > beam:
+                    blk = sorted(sorted(blk, key=lambda i: (-nxt[i][4], i))[:beam])
+                kept.extend(blk)
+            nxt = [nxt[i] for i in kept]
+        level = nxt
+    qd = np.full(A, -np.inf)
+    stacks = np.stack([nd[2] for nd in level])
+    vmax = Q.qvalues(stacks, world.w64, A).max(axis=1)
+    for nd, v in zip(level, vmax):
+        qd[nd[0]] = max(qd[nd[0]], nd[3] + gamma ** d * float(v))
+    q0 = Q.qvalues(stack, world.w64, A)
+    if not correction:
+        return Result(action=argmax_low(qd), q=qd.copy(), q_d=qd, ties=tie_set(qd))
+    pi_o = argmax_low(q0)
+    delta = np.empty(A)
+    for a, (p, s, r) in enumerate(children(world, pos, stack, A)):
+        delta[a] = r + gamma * float(qmax(world, s[None], A)[0]) - q0[a]
+    do = abs(delta[pi_o])
+    de = float(np.mean([abs(delta[a]) for a in range(A) if a != pi_o]))
+    if mode == "eq6":
+        B = penalty(de, do, A, d)
+    else:
+        from . import gev
+        B = gev.exact_gap(de / math.sqrt(2.0), do / math.sqrt(2.0), A, d)
+    q = qd.copy()
+    for a in range(A):
+        if a != pi_o:
+            q[a] = qd[a] - c * gamma ** d * B
+    return Result(action=argmax_low(q), q=q, q_d=qd, q0=q0, pi_o=pi_o, delta=delta, B=B, ties=tie_set(q))
