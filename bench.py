@@ -130,7 +130,7 @@ def run_mixed(args):
     pos_t = torch.from_numpy(pos).to(dev)
     st_t = torch.from_numpy(st).to(dev)
     act_t = torch.zeros(n, dtype=torch.int32, device=dev)
-    q_t = torch.zeros(int(Av.sum()), dtype=torch.float32, device=dev)
+    q_t = torch.zeros(n, 18, dtype=torch.float32, device=dev)        # [n][18] rows (entries >= A are -inf)
     corr = bcts.correction(True, C)
     stream = torch.cuda.Stream()
     tuned = None
