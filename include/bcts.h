@@ -218,6 +218,21 @@ bcts_status bcts_serve_config(bcts_ctx* ctx, int32_t max_batch, int32_t max_infl
 /* Device bytes one request of (depth, A) reserves while admitted.         */
 size_t bcts_request_bytes(int32_t depth, int32_t A);
 
+/* ---- pruned search ------------------------------------------------------ */
+/* Batch-BFS gives the return of every node of a level at once, which the
+ * paper suggests for early pruning with an index array of surviving nodes
+ * (Sec. 4; left there as future work).  With beam B > 0 every later search
+ * of the context (host, device, graph and served) cuts levels 2..d-1: inside
+ * each root action's sub-tree only the B nodes with the largest discounted
+ * return so far (FP32, lowest index on ties) are expanded further, their
+ * root-local indices kept in a keep list per level; the leaves are all
+ * children of the kept depth-(d-1) nodes, and Q_d(a0) is the best of a0's
+ * surviving leaves.  The depth-0/1 quantities of the correction are not
+ * affected.  B = 0 (the default) is the exhaustive search; a level whose
+ * blocks hold at most B nodes is not cut, so B >= A^(d-2) changes nothing.
+ * BCTS_E_INVAL outside [0, 256].                                            */
+bcts_status bcts_set_beam(bcts_ctx* ctx, int32_t beam);
+
 /* ---- learned forward-model world (Sec. 4.1's runtime study) ------------- */
 /* The paper also times tree search over a deep network that mimics a learned
  * forward model: three hidden layers of width 100 fed a 100-dimensional

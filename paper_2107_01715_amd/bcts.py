@@ -40,7 +40,7 @@ EXPORTS = (
     "bcts_submit", "bcts_progress", "bcts_poll", "bcts_serve_config", "bcts_request_bytes",
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
-    "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device",
+    "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK = 0, 1, 2, 3
 
@@ -98,6 +98,7 @@ _autotune = _sig("bcts_autotune", c_int32, _P, c_int32, _P, _P, _P, _P, c_float,
                  POINTER(ctypes.c_int64))
 
 _set_mlp = _sig("bcts_set_mlp", c_int32, _P, c_int32, _P, c_size_t)
+_set_beam = _sig("bcts_set_beam", c_int32, _P, c_int32)
 _mlp_search = _sig("bcts_mlp_search", c_int32, _P, c_int32, _P, c_int32, c_float, CorrectionC, _P, _P)
 _mlp_search_device = _sig("bcts_mlp_search_device", c_int32, _P, c_int32, _P, c_int32, c_float, CorrectionC, _P, _P,
                           _P)
@@ -202,27 +203,31 @@ def bcts_search_batch(ctx, pos, stacks, depth, A, gamma: float, corr: Correction
     return act, q
 
 
-def _dev(t, dtype):
+def _dev(t, dtype, min_numel: int = 0):
     assert t.is_cuda and t.is_contiguous() and t.dtype == dtype, (t.device, t.dtype)
+    if t.numel() < min_numel:
+        raise ValueError(f"device buffer holds {t.numel()} elements, the call writes {min_numel}")
     return c_void_p(t.data_ptr())
 
 
 def bcts_search_batch_device(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, stream=None):
+    n = pos_t.shape[0]
     d = _arr(depth, np.int32)
     a = _arr(A, np.int32)
     s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
     _check(ctx, _search_batch_device(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8),
-                                     _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32),
-                                     _dev(q_t, torch.float32), s))
+                                     _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32, n),
+                                     _dev(q_t, torch.float32, n * MAX_A), s))
 
 
 def bcts_search_batch_graph(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, replays=1, stream=None):
+    n = pos_t.shape[0]
     d = _arr(depth, np.int32)
     a = _arr(A, np.int32)
     s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
     _check(ctx, _search_batch_graph(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8),
-                                    _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32),
-                                    _dev(q_t, torch.float32), replays, s))
+                                    _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32, n),
+                                    _dev(q_t, torch.float32, n * MAX_A), replays, s))
 
 
 def bcts_submit(ctx, pos, stack, depth: int, A: int, gamma: float, corr: CorrectionC) -> int:
@@ -259,6 +264,10 @@ def bcts_request_bytes(depth: int, A: int) -> int:
     return int(_request_bytes(depth, A))
 
 
+def bcts_set_beam(ctx, beam: int):
+    _check(ctx, _set_beam(ctx, beam))
+
+
 def bcts_set_mlp(ctx, A: int, blob):
     b = _arr(blob, np.float32)
     _check(ctx, _set_mlp(ctx, A, _ptr(b), b.size))
@@ -276,9 +285,11 @@ def bcts_mlp_search(ctx, states, depth: int, A: int, gamma: float, corr: Correct
 
 
 def bcts_mlp_search_device(ctx, states_t, depth: int, gamma: float, corr: CorrectionC, act_t, q_t, stream=None):
+    """q_t: float32 [n][A] with A the model's action count (its last dimension)."""
     s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
-    _check(ctx, _mlp_search_device(ctx, states_t.shape[0], _dev(states_t, torch.float32), depth, gamma, corr,
-                                   _dev(act_t, torch.int32), _dev(q_t, torch.float32), s))
+    n = states_t.shape[0]
+    _check(ctx, _mlp_search_device(ctx, n, _dev(states_t, torch.float32, n * 100), depth, gamma, corr,
+                                   _dev(act_t, torch.int32, n), _dev(q_t, torch.float32, n * q_t.shape[-1]), s))
 
 
 def bcts_debug_expand(ctx, pos, stack, depth: int, A: int):
@@ -332,8 +343,10 @@ def bcts_autotune(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, reps=
     a = _arr(A, np.int32)
     s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
     out = (ctypes.c_int64 * 4)()
-    _check(ctx, _autotune(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8), _ptr(d),
-                          _ptr(a), gamma, corr, _dev(act_t, torch.int32), _dev(q_t, torch.float32), reps, s, out))
+    n = pos_t.shape[0]
+    _check(ctx, _autotune(ctx, n, _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8), _ptr(d),
+                          _ptr(a), gamma, corr, _dev(act_t, torch.int32, n), _dev(q_t, torch.float32, n * MAX_A),
+                          reps, s, out))
     return {"fused": int(out[0]), "round": int(out[1]), "chunk": int(out[2]), "us_per_search": int(out[3])}
 
 

@@ -86,6 +86,8 @@ struct Plan {
   long long lvl_count[kMaxD + 1] = {0};
   std::vector<int> lvl_root[kMaxD + 1];
   std::vector<long long> lvl_start[kMaxD + 1];
+  int beam = 0;                        // beam of the cut levels (0: exhaustive)
+  long long keep_count[kMaxD + 1] = {0};   // keep-list entries of level k over all roots
   long long chunk = 0;                 // max items of a chunk
   bool fused = false;                  // conv stack fused per sibling group
   std::vector<FusedGroup> groups;      // sibling groups in item order
@@ -96,7 +98,8 @@ struct Plan {
   size_t o_root_pos = 0, o_root_stack = 0, o_roots = 0, o_segs = 0, o_V = 0, o_q0 = 0,
          o_desc = 0, o_ws = 0, o_act = 0, o_q = 0, total = 0;
   size_t o_pos[kMaxD + 1] = {0}, o_frames[kMaxD + 1] = {0}, o_ret[kMaxD + 1] = {0},
-         o_rew[kMaxD + 1] = {0}, o_lroot[kMaxD + 1] = {0}, o_lstart[kMaxD + 1] = {0};
+         o_rew[kMaxD + 1] = {0}, o_lroot[kMaxD + 1] = {0}, o_lstart[kMaxD + 1] = {0},
+         o_keep[kMaxD + 1] = {0};
   size_t table_bytes = 0;   // bytes of host tables uploaded (roots .. lstart)
 };
 
@@ -113,6 +116,7 @@ struct bcts_ctx {
   long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
   bool fused = true;
+  int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
   // weights
   void* wmem = nullptr;
   size_t wbytes = 0;
@@ -235,8 +239,9 @@ bcts_status validate_pos(bcts_ctx* c, int n, const int32_t* pos) {
 // single root-kind eval (debug Q-network on stacks).
 void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
                const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
-               bool host_io, bool fused = false) {
+               bool host_io, bool fused = false, int beam = 0) {
   p = Plan();
+  p.beam = beam;
   p.fused = fused && prec != P_FP32;
   p.n = n;
   p.roots.resize(n);
@@ -250,18 +255,33 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     ri.gamma_d = (float)std::pow((double)gamma, (double)ri.d);
     ri.corr = (corr.enabled && ri.d >= 1) ? 1 : 0;
     ri.q_stride = q_stride;
-    long long cnt = 1;
+    // nodes per level: A children of each kept node of the level above; a
+    // beam cuts levels 2..d-1 to `beam` nodes per root action where a root
+    // action's block is larger
+    ri.lcnt[0] = 1;
+    ri.kbase[0] = -1;
+    long long kept = 1;
     for (int k = 1; k <= kMaxD; ++k) {
-      cnt *= ri.A;
+      ri.kbase[k] = -1;
       if (k <= ri.d) {
+        const long long cnt = kept * ri.A;
+        ri.lcnt[k] = cnt;
         ri.base[k] = p.lvl_count[k];
         p.lvl_root[k].push_back(r);
         p.lvl_start[k].push_back(p.lvl_count[k]);
         p.lvl_count[k] += cnt;
+        kept = cnt;
+        if (beam > 0 && k >= 2 && k <= ri.d - 1 && cnt / ri.A > beam) {
+          ri.kbase[k] = p.keep_count[k];
+          p.keep_count[k] += (long long)ri.A * beam;
+          kept = (long long)ri.A * beam;
+        }
       } else {
         ri.base[k] = -1;
+        ri.lcnt[k] = 0;
       }
     }
+    ri.leaf_blk = ri.d >= 1 ? ri.lcnt[ri.d] / ri.A : 0;
     if (ri.corr) {
       double pe, po;
       if (corr.mode == BCTS_CORR_EXACT_GEV) gev_coeffs(ri.A, ri.d, &pe, &po);
@@ -276,8 +296,7 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     RootInfo& ri = p.roots[r];
     ri.leaf_item = ri.d1_item = ri.root_item = -1;
     if (ri.d >= 1) {
-      long long cnt = 1;
-      for (int k = 0; k < ri.d; ++k) cnt *= ri.A;
+      const long long cnt = ri.lcnt[ri.d];
       p.segs.push_back(Seg{item, r, ri.d, ri.A, 0});
       ri.leaf_item = item;
       item += cnt;
@@ -298,8 +317,7 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
   // nodes of a root, a root alone; chunks hold whole groups
   for (const Seg& sg : p.segs) {
     const RootInfo& ri = p.roots[sg.root];
-    long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : 1);
-    if (sg.kind == 0) for (int k = 0; k < ri.d; ++k) cnt *= ri.A;
+    const long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : ri.lcnt[ri.d]);
     const int gsz = sg.kind == 2 ? 1 : ri.A;
     for (long long j = 0; j < cnt; j += gsz) p.groups.push_back(FusedGroup{sg.item0 + j, gsz, 0});
   }
@@ -345,6 +363,7 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     p.o_frames[k] = take((size_t)p.lvl_count[k] * kFrameBytes);
     p.o_ret[k] = take((size_t)p.lvl_count[k] * sizeof(float));
     p.o_rew[k] = take((size_t)p.lvl_count[k]);
+    if (p.keep_count[k] > 0) p.o_keep[k] = take(sizeof(int) * (size_t)p.keep_count[k]);
   }
   p.o_V = take(sizeof(float) * p.n_items);
   p.o_q0 = take(sizeof(float) * (size_t)n * kMaxA);
@@ -357,7 +376,8 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
 void plan_search(bcts_ctx* c, Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
                  const bcts_correction& corr, int q_stride, bool host_io) {
   const bool fz = c->fused && c->prec != P_FP32;
-  make_plan(p, n, depth, A, gamma, corr, q_stride, fz ? c->fused_chunk_items : c->chunk_items, c->prec, host_io, fz);
+  make_plan(p, n, depth, A, gamma, corr, q_stride, fz ? c->fused_chunk_items : c->chunk_items, c->prec, host_io, fz,
+            c->beam);
 }
 
 // Copy the plan's tables to `arena` through the pinned staging buffer `h`
@@ -467,15 +487,23 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
                   reinterpret_cast<const long long*>(A + p.o_lstart[k]), (int)p.lvl_root[k].size()};
     launch_expand(k, p.lvl_count[k], lr, roots, d_pos,
                   k > 1 ? reinterpret_cast<const uint8_t*>(A + p.o_pos[k - 1]) : nullptr,
-                  k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr, c->env, (float)g,
+                  k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr,
+                  k > 1 && p.keep_count[k - 1] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k - 1]) : nullptr,
+                  c->env, (float)g,
                   reinterpret_cast<uint8_t*>(A + p.o_pos[k]), reinterpret_cast<uint8_t*>(A + p.o_frames[k]),
                   reinterpret_cast<float*>(A + p.o_ret[k]), reinterpret_cast<uint8_t*>(A + p.o_rew[k]), s);
+    if (p.keep_count[k] > 0)
+      launch_prune(k, (int)p.lvl_root[k].size(), lr, roots, reinterpret_cast<const float*>(A + p.o_ret[k]),
+                   reinterpret_cast<int*>(A + p.o_keep[k]), p.beam, s);
     if (timed) HIPCHECK(c, hipEventRecord(ev[k], s));
     g *= gamma;
   }
   FrameBases fb{};
   fb.level_frames[0] = d_stacks;
-  for (int k = 1; k <= p.maxd; ++k) fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
+  for (int k = 1; k <= p.maxd; ++k) {
+    fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
+    fb.keep[k] = p.keep_count[k] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k]) : nullptr;
+  }
   float* V = reinterpret_cast<float*>(A + p.o_V);
   float* q0 = reinterpret_cast<float*>(A + p.o_q0);
   {
@@ -712,10 +740,10 @@ struct ServeEngine {
     for (int i = 0; i < n; ++i) { dep[i] = queue[i].d; Av[i] = queue[i].A; }
     Plan p;
     const bool fz = c->fused && c->prec != P_FP32;
-    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz);
+    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam);
     while (p.total > slot_cap && n > 1) {   // alignment slack: shrink the batch
       --n;
-      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz);
+      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam);
     }
     if (p.total > slot_cap) return fail(c, BCTS_E_NOMEM, "request does not fit a serving slot");
     if (sl.arena_bytes < slot_cap) {
@@ -1143,7 +1171,7 @@ bcts_status bcts_debug_expand(bcts_ctx* c, const int32_t* pos, const uint8_t* st
                   reinterpret_cast<const long long*>(Ar + p.o_lstart[k]), (int)p.lvl_root[k].size()};
     launch_expand(k, p.lvl_count[k], lr, roots, reinterpret_cast<const int32_t*>(Ar + p.o_root_pos),
                   k > 1 ? reinterpret_cast<const uint8_t*>(Ar + p.o_pos[k - 1]) : nullptr,
-                  k > 1 ? reinterpret_cast<const float*>(Ar + p.o_ret[k - 1]) : nullptr, c->env, 1.f,
+                  k > 1 ? reinterpret_cast<const float*>(Ar + p.o_ret[k - 1]) : nullptr, nullptr, c->env, 1.f,
                   reinterpret_cast<uint8_t*>(Ar + p.o_pos[k]), reinterpret_cast<uint8_t*>(Ar + p.o_frames[k]),
                   reinterpret_cast<float*>(Ar + p.o_ret[k]), reinterpret_cast<uint8_t*>(Ar + p.o_rew[k]), s);
   }
@@ -1379,6 +1407,14 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
   out_best[1] = best[1];
   out_best[2] = best[2];
   out_best[3] = (int64_t)(best_ms * 1000.0);   // microseconds per search
+  return BCTS_OK;
+}
+
+bcts_status bcts_set_beam(bcts_ctx* c, int32_t beam) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (beam < 0 || beam > kMaxBeam) return fail(c, BCTS_E_INVAL, "beam=%d outside [0,%d]", beam, kMaxBeam);
+  c->beam = beam;
   return BCTS_OK;
 }
 

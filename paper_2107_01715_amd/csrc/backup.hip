@@ -2,8 +2,10 @@
 //
 //  * Backup (Eq. 1 / Alg. 1, final steps): a leaf's value is its discounted
 //    return plus gamma^d max_a Q(leaf, a); the leaves of root action a0 are
-//    the contiguous block [a0 A^(d-1), (a0+1) A^(d-1)) of the root's leaves,
-//    so Q_d(a0) is a max-reduction over that block.
+//    the contiguous block [a0 A^(d-1), (a0+1) A^(d-1)) of the root's leaves
+//    (blocks of leaf_blk leaves when a beam cut the tree: the surviving
+//    leaves stay grouped by root action), so Q_d(a0) is a max-reduction over
+//    that block.
 //  * Correction (Eq. 3 with B of Eq. 6 or the exact gap of Lemma 3.2):
 //    pi_o = argmax of the network at the root, the depth-1 Bellman errors
 //    delta(a) = r_a + gamma V(s_1^a) - Q_0(a) (Prop. 3.6), d_o = |delta(pi_o)|,
@@ -37,8 +39,7 @@ backup_kernel(int n_roots, const RootInfo* __restrict__ roots, const float* __re
   if (d == 0) {
     if (lane < A) q[lane] = q0[(long long)r * kMaxA + lane];
   } else {
-    long long blk = 1;
-    for (int i = 1; i < d; ++i) blk *= A;
+    const long long blk = ri.leaf_blk;          // A^(d-1), fewer when a beam cut the tree
     const float* ret = level_ret.ret[d] + ri.base[d];
     const float* v = V + ri.leaf_item;
     for (int a0 = 0; a0 < A; ++a0) {

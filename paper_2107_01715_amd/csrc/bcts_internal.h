@@ -24,6 +24,7 @@
 namespace bcts {
 
 constexpr int kFrame = 84;
+constexpr int kMaxBeam = 256;           // largest beam of the pruned search
 constexpr int kFrameBytes = 84 * 84;
 constexpr int kSprites = 8;
 constexpr int kMaxA = 18;
@@ -38,6 +39,9 @@ struct RootInfo {
   int q_stride;           // output row stride of out_q
   int pad_;
   long long base[kMaxD + 1];   // first node of this root at level k (k >= 1)
+  long long lcnt[kMaxD + 1];   // nodes of this root at level k (A^k unless a beam cuts earlier levels)
+  long long kbase[kMaxD + 1];  // level k cut by the beam: first entry of this root's keep list, else -1
+  long long leaf_blk;          // leaves per root action (A^(d-1) unless cut)
   long long leaf_item;         // first leaf eval item (d >= 1), else -1
   long long d1_item;           // first depth-1 eval item (d >= 2 and corr), else -1
   long long root_item;         // root eval item, else -1
@@ -72,7 +76,16 @@ struct ItemDesc {
 // each); level_frames[0] is the root stack array [n][4][7056].
 struct FrameBases {
   const uint8_t* level_frames[kMaxD + 1];
+  const int* keep[kMaxD + 1];  // keep lists of cut levels (root-local node indices)
 };
+
+// Parent of root-local node j at level k >= 2: node j / A of level k - 1
+// counted among that level's kept nodes (the keep list maps it back to a
+// root-local index when the level was cut).
+__device__ __forceinline__ long long parent_local(const RootInfo& ri, const int* const* keep, int k, long long j) {
+  const long long i = j / ri.A;
+  return ri.kbase[k - 1] >= 0 ? (long long)keep[k - 1][ri.kbase[k - 1] + i] : i;
+}
 
 // A sibling group: consecutive eval items whose stacks share channels 0..2
 // (the A children of one node, the A depth-1 nodes of a root, or one root).
@@ -144,9 +157,15 @@ void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long 
 
 // ---- launchers (each in the TU that defines its kernels) ----------------
 void launch_expand(int k, long long n_nodes, LevelRoots lr, const RootInfo* roots,
-                   const int* root_pos, const uint8_t* prev_pos, const float* prev_ret,
+                   const int* root_pos, const uint8_t* prev_pos, const float* prev_ret, const int* prev_keep,
                    const EnvTables& env, float gamma_pow, uint8_t* pos, uint8_t* frames,
                    float* ret, uint8_t* rew, hipStream_t s);
+
+// Beam cut of level k: for every root whose level k is cut and every root
+// action a0, the `beam` nodes of a0's block with the largest return (lowest
+// index on ties) go, ascending, to keep[kbase + a0 * beam ..].
+void launch_prune(int k, int n_level_roots, LevelRoots lr, const RootInfo* roots, const float* ret_k, int* keep_k,
+                  int beam, hipStream_t s);
 
 void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, int nsegs,
                       const RootInfo* roots, const FrameBases& fb, ItemDesc* out,

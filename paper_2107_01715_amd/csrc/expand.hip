@@ -90,10 +90,45 @@ __device__ __forceinline__ int find_root(const LevelRoots& lr, long long node) {
   return lo;
 }
 
+// Beam cut of level k, one workgroup per (root, root action a0): a0's
+// block of the level (c contiguous root-local nodes, c <= A * beam) is ranked
+// by return, descending, ties to the lower index (rank of i = number of j
+// with ret_j > ret_i, or ret_j == ret_i and j < i: exact, order-free); the
+// nodes of rank < beam are written ascending to the keep list.
+constexpr int kPruneThreads = 256;
+constexpr int kMaxBlock = kMaxA * kMaxBeam;
+
+__global__ void __launch_bounds__(kPruneThreads)
+prune_kernel(int k, LevelRoots lr, const RootInfo* __restrict__ roots, const float* __restrict__ ret_k,
+             int* __restrict__ keep_k, int beam) {
+  __shared__ float v[kMaxBlock];
+  __shared__ int kept[kMaxBlock];
+  const int r = lr.root[blockIdx.x / kMaxA], a0 = blockIdx.x % kMaxA;
+  const RootInfo& ri = roots[r];
+  if (a0 >= ri.A || ri.kbase[k] < 0) return;
+  const int c = (int)(ri.lcnt[k] / ri.A);          // block size, <= A * beam
+  const long long first = ri.base[k] + (long long)a0 * c;
+  for (int i = threadIdx.x; i < c; i += kPruneThreads) v[i] = ret_k[first + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < c; i += kPruneThreads) {
+    const float x = v[i];
+    int rank = 0;
+    for (int j = 0; j < c; ++j) rank += (v[j] > x || (v[j] == x && j < i)) ? 1 : 0;
+    kept[i] = rank < beam ? 1 : 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < c; i += kPruneThreads) {
+    if (!kept[i]) continue;
+    int pos = 0;
+    for (int j = 0; j < i; ++j) pos += kept[j];
+    keep_k[ri.kbase[k] + (long long)a0 * beam + pos] = a0 * c + i;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
 expand_kernel(int k, long long n_nodes, LevelRoots lr, const RootInfo* __restrict__ roots,
               const int* __restrict__ root_pos, const uint8_t* __restrict__ prev_pos,
-              const float* __restrict__ prev_ret, EnvTables env, float gamma_pow,
+              const float* __restrict__ prev_ret, const int* __restrict__ prev_keep, EnvTables env, float gamma_pow,
               uint8_t* __restrict__ pos, uint8_t* __restrict__ frames, float* __restrict__ ret,
               uint8_t* __restrict__ rew_out) {
   __shared__ int s_pos[kNB][kSprites][2];
@@ -113,7 +148,8 @@ expand_kernel(int k, long long n_nodes, LevelRoots lr, const RootInfo* __restric
       const long long j = node - lr.start[ri];
       const int A = roots[r].A;
       const int a = (int)(j % A);
-      const long long pj = j / A;
+      const long long pj = roots[r].kbase[k - 1] >= 0 && k > 1 ? (long long)prev_keep[roots[r].kbase[k - 1] + j / A]
+                                                              : j / A;
       int p[kSprites][2];
       float pret = 0.f;
       if (k == 1) {
@@ -151,7 +187,7 @@ expand_kernel(int k, long long n_nodes, LevelRoots lr, const RootInfo* __restric
         w[q] = (unsigned)p[2 * q][0] | ((unsigned)p[2 * q][1] << 8) |
                ((unsigned)p[2 * q + 1][0] << 16) | ((unsigned)p[2 * q + 1][1] << 24);
       *reinterpret_cast<uint4*>(pos + node * 16) = make_uint4(w[0], w[1], w[2], w[3]);
-      ret[node] = pret + gamma_pow * (float)rew;
+      ret[node] = fmaf(gamma_pow, (float)rew, pret);   // one rounding (a beam ranks these)
       rew_out[node] = (uint8_t)rew;
       for (int i = 0; i < kSprites; ++i) {
         s_pos[tid][i][0] = p[i][0];
@@ -206,14 +242,21 @@ expand_kernel(int k, long long n_nodes, LevelRoots lr, const RootInfo* __restric
 }  // namespace
 
 void launch_expand(int k, long long n_nodes, LevelRoots lr, const RootInfo* roots,
-                   const int* root_pos, const uint8_t* prev_pos, const float* prev_ret,
+                   const int* root_pos, const uint8_t* prev_pos, const float* prev_ret, const int* prev_keep,
                    const EnvTables& env, float gamma_pow, uint8_t* pos, uint8_t* frames,
                    float* ret, uint8_t* rew, hipStream_t s) {
   if (n_nodes <= 0) return;
   long long groups = (n_nodes + kNB - 1) / kNB;
   int grid = (int)(groups < 65536 ? groups : 65536);
   hipLaunchKernelGGL(expand_kernel, dim3(grid), dim3(kThreads), 0, s, k, n_nodes, lr, roots,
-                     root_pos, prev_pos, prev_ret, env, gamma_pow, pos, frames, ret, rew);
+                     root_pos, prev_pos, prev_ret, prev_keep, env, gamma_pow, pos, frames, ret, rew);
+}
+
+void launch_prune(int k, int n_level_roots, LevelRoots lr, const RootInfo* roots, const float* ret_k, int* keep_k,
+                  int beam, hipStream_t s) {
+  if (n_level_roots <= 0) return;
+  hipLaunchKernelGGL(prune_kernel, dim3((unsigned)n_level_roots * kMaxA), dim3(kPruneThreads), 0, s, k, lr, roots,
+                     ret_k, keep_k, beam);
 }
 
 }  // namespace bcts

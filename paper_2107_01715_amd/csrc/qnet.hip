@@ -423,12 +423,18 @@ __global__ void item_desc_kernel(long long item_begin, long long n_items, const 
   const long long j = item - sg.item0;
   ItemDesc d;
   const int m = sg.level;
+  // root-local index of the ancestor at each level m, m - 1, .. (through the
+  // keep lists of levels cut by a beam)
+  long long anc[4];
+  anc[3] = j;
+  for (int c = 2; c >= 0; --c) {
+    const int l = m - 3 + c;          // level of ancestor c
+    anc[c] = l >= 1 ? parent_local(ri, fb.keep, l + 1, anc[c + 1]) : -1;
+  }
   for (int c = 0; c < 4; ++c) {
     const int l = m - 3 + c;
     if (l >= 1) {
-      long long div = 1;
-      for (int q = 0; q < m - l; ++q) div *= sg.A;
-      d.frame[c] = fb.level_frames[l] + (ri.base[l] + j / div) * (long long)kFrameBytes;
+      d.frame[c] = fb.level_frames[l] + (ri.base[l] + anc[c]) * (long long)kFrameBytes;
     } else {
       d.frame[c] = fb.level_frames[0] + ((long long)sg.root * 4 + 3 + l) * (long long)kFrameBytes;
     }

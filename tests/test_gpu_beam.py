@@ -1,0 +1,128 @@
+"""Pruned search on the GPU (through the C ABI): FP32 parity with the oracle's
+pruned search (oracle.search.search_beam, same FP32 ranking), bit-identity
+with the exhaustive search when the beam cuts nothing, the sub-tree bound
+(a pruned root value never exceeds the exhaustive one; both paths score the
+shared leaves identically, so the bound holds exactly), and the same bits
+through the graph and served forms."""
+import numpy as np
+import pytest
+
+from oracle import qnet as Q, search as S
+from paper_2107_01715_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 0.99
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_01715_amd import bcts
+    return bcts
+
+
+@pytest.fixture(scope="module")
+def setup(lib):
+    ep = W.env_params(1001)
+    w = W.qnet_weights(7)
+    ctx = lib.Context(0)
+    ctx.set_env(ep.delta, ep.vel)
+    ctx.set_qnet(W.qnet_blob(w))
+    world = S.World(ep.delta, ep.vel, Q.prepare(w))
+    yield ctx, world
+    ctx.set_beam(0)
+    ctx.close()
+
+
+def search(lib, ctx, pos, st, d, A, beam, prec=None):
+    ctx.set_precision(lib.FP32 if prec is None else prec)
+    ctx.set_beam(beam)
+    try:
+        act, q = ctx.search_batch(pos, st, np.asarray(d, np.int32), np.asarray(A, np.int32), GAMMA,
+                                  lib.correction(True, 1.0))
+    finally:
+        ctx.set_beam(0)
+    return act, q
+
+
+@pytest.mark.parametrize("A,d,beam,n", [(4, 3, 1, 6), (4, 3, 2, 6), (6, 3, 2, 4), (3, 4, 2, 4), (2, 5, 3, 3)])
+def test_parity_with_pruned_oracle(lib, setup, A, d, beam, n):
+    ctx, world = setup
+    pos, st = W.roots(1001, n)
+    act, q = search(lib, ctx, pos, st, [d] * n, [A] * n, beam)
+    for r in range(n):
+        ref = S.search_beam(world, pos[r], st[r], d, A, GAMMA, beam)
+        qo = np.asarray(ref.q)
+        err = np.abs(q[r, :A].astype(np.float64) - qo).max()
+        assert err <= RTOL * np.abs(qo).max() + 1e-7, (r, q[r, :A], qo)
+        assert act[r] == ref.action or act[r] in ref.ties
+
+
+def test_mixed_batch_with_cuts(lib, setup):
+    """Roots of different (A, d) in one batch: some levels cut, some not."""
+    ctx, world = setup
+    A = np.array([4, 6, 3, 18, 4, 2], np.int32)
+    d = np.array([3, 3, 4, 2, 1, 5], np.int32)
+    pos, st = W.roots(1002, len(A))
+    act, q = search(lib, ctx, pos, st, d, A, 2)
+    for r in range(len(A)):
+        ref = S.search_beam(world, pos[r], st[r], int(d[r]), int(A[r]), GAMMA, 2)
+        qo = np.asarray(ref.q)
+        err = np.abs(q[r, :A[r]].astype(np.float64) - qo).max()
+        assert err <= RTOL * np.abs(qo).max() + 1e-7, (r, q[r, :A[r]], qo)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_wide_beam_is_exhaustive_and_bound_holds(lib, setup, prec):
+    ctx, _ = setup
+    p = lib.FP32 if prec == "fp32" else lib.BF16
+    pos, st = W.roots(1003, 8)
+    d, A = [3] * 8, [6] * 8
+    a0, q0 = search(lib, ctx, pos, st, d, A, 0, p)
+    aw, qw = search(lib, ctx, pos, st, d, A, 6, p)      # blocks of 6 at level 2: nothing cut
+    assert np.array_equal(a0, aw) and np.array_equal(q0, qw)
+    for beam in (1, 3):
+        _, qb = search(lib, ctx, pos, st, d, A, beam, p)
+        assert np.all(qb[:, :6] <= q0[:, :6])
+
+
+def test_graph_and_served_forms_follow_the_beam(lib, setup):
+    import torch
+    ctx, _ = setup
+    n, A, d = 5, 4, 3
+    pos, st = W.roots(1004, n)
+    act_h, q_h = search(lib, ctx, pos, st, [d] * n, [A] * n, 1)
+    dev = torch.device("cuda:0")
+    pt, stt = torch.from_numpy(pos).to(dev), torch.from_numpy(st).to(dev)
+    at = torch.zeros(n, dtype=torch.int32, device=dev)
+    qt = torch.zeros(n, 18, dtype=torch.float32, device=dev)
+    ctx.set_precision(lib.FP32)
+    ctx.set_beam(1)
+    try:
+        ctx.search_batch_graph(pt, stt, np.full(n, d, np.int32), np.full(n, A, np.int32), GAMMA,
+                               lib.correction(True, 1.0), at, qt, replays=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(at.cpu().numpy(), act_h)
+        assert np.array_equal(qt.cpu().numpy(), q_h)
+        tickets = [ctx.submit(pos[r], st[r], d, A, GAMMA, lib.correction(True, 1.0)) for r in range(n)]
+        for r, t in enumerate(tickets):
+            while True:
+                ctx.progress()
+                res = ctx.poll(t, A)
+                if res is not None:
+                    break
+            assert res[0] == act_h[r] and np.array_equal(res[1], q_h[r, :A])
+    finally:
+        ctx.set_beam(0)
+
+
+def test_beam_argument(lib, setup):
+    ctx, _ = setup
+    for bad in (-1, 257):
+        with pytest.raises(lib.BctsError) as e:
+            ctx.set_beam(bad)
+        assert e.value.status == lib.E_INVAL
