@@ -29,10 +29,14 @@ Two further workloads print their own JSON line:
                     model with three hidden layers of width 100, A = 2 and
                     10): GPU time per search of one root against depth, the
                     FP64 oracle's depth-first search on the host beside it,
-                    and the batched throughput of 64 roots.
+                    and the batched throughput of 64 roots;
+  --workload beam   pruned search: 64 roots at A=18, depth 4, BF16,
+                    exhaustive against beams of 4, 16 and 64 nodes per root
+                    action: time per step, leaves scored, and root-action
+                    agreement with the exhaustive search.
 
     python bench.py [--steps K] [--warmup W] [--precision bf16|fp8|fp32]
-                    [--workload headline|mixed|serve|mlp]
+                    [--workload headline|mixed|serve|mlp|beam]
 """
 from __future__ import annotations
 
@@ -336,6 +340,63 @@ def run_mlp(args):
     print(json.dumps(out))
 
 
+def run_beam(args):
+    """Pruned search against the exhaustive one at A=18, depth 4 (64 roots)."""
+    import numpy as np
+    import torch
+    from paper_2107_01715_amd import bcts, workload as W
+    n, A_, d = 64, 18, 4
+    pos, st = W.roots(INSTANCE_SEED, n)
+    ctx = _setup(INSTANCE_SEED, n)
+    ctx.set_precision({"bf16": bcts.BF16, "fp8": bcts.FP8, "fp32": bcts.FP32}[args.precision])
+    dev = torch.device("cuda:0")
+    pos_t, st_t = torch.from_numpy(pos).to(dev), torch.from_numpy(st).to(dev)
+    act_t = torch.zeros(n, dtype=torch.int32, device=dev)
+    q_t = torch.zeros(n, 18, dtype=torch.float32, device=dev)
+    dv, Av = np.full(n, d, np.int32), np.full(n, A_, np.int32)
+    corr = bcts.correction(True, C)
+    stream = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows, ref = [], None
+    for beam in (0, 64, 16, 4):
+        ctx.set_beam(beam)
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                ctx.search_batch_device(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, stream=stream)
+            e0.record(stream)
+            for _ in range(args.steps):
+                ctx.search_batch_device(pos_t, st_t, dv, Av, GAMMA, corr, act_t, q_t, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        act, q = act_t.cpu().numpy().copy(), q_t.cpu().numpy().copy()
+        if beam == 0:
+            ref = (act, q)
+        per_a0 = 1
+        for k in range(2, d):
+            per_a0 = per_a0 * A_ if beam == 0 or per_a0 * A_ <= beam else beam
+        leaves = n * A_ * per_a0 * A_
+        agree = int((act == ref[0]).sum())
+        rows.append({"beam": beam, "ms_per_step": ms, "leaves_scored": leaves,
+                     "leaf_evals_per_s": leaves / (ms * 1e-3), "root_action_agreement": agree / n,
+                     "max_root_q_drop": float((ref[1][:, :A_] - q[:, :A_]).max())})
+        print(f"# beam {beam}: {ms:.2f} ms, {leaves} leaves, agreement {agree}/{n}", file=sys.stderr, flush=True)
+    ctx.set_beam(0)
+    ctx.close()
+    b16 = [r for r in rows if r["beam"] == 16][0]
+    out = {
+        "metric": "pruned search time per step (A=18, depth 4, beam 16 per root action)", "value": b16["ms_per_step"],
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": b16["ms_per_step"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8_e4m3", "fp32": "f32"}[args.precision],
+        "data": "synthetic (seeded sprite world, random Kaiming-uniform Nature-DQN)",
+        "config": {"workload": "64 roots, A=18, depth 4, gamma 0.99, BCTS c=1.0; beams 0 (exhaustive), 64, 16, 4 "
+                               "nodes per root action at levels 2-3", "precision": args.precision},
+        "beams": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,7 +407,7 @@ def main():
     ap.add_argument("--skip-fp32-single", action="store_true")
     ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
     ap.add_argument("--retune", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp", "beam"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--quick", action="store_true",
                     help="headline precision only (no comparison forms, no accuracy): for profiler runs")
@@ -361,6 +422,8 @@ def main():
         return run_serve(args)
     if args.workload == "mlp":
         return run_mlp(args)
+    if args.workload == "beam":
+        return run_beam(args)
 
     # CPU baseline first: the worker pool forks before the GPU is touched
     cpu, oracle_ref = (None, {})
