@@ -293,24 +293,47 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
     lds_barrier();       // the round's frames are staged
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
+    // Software-pipelined over the round's items: item t+1's pixel operands
+    // are read and its 14 MFMAs issued before item t's epilogue, so the
+    // epilogue's VALU work runs while the matrix core is busy.  All T items
+    // are computed: a slot past the group's last item holds a staged copy of
+    // a valid frame, and its x1 rows are never read by conv2.
     {
       const float sc = a.acc_scale[0], o8 = a.out_s8[0];
+      V pv[kF1][2];
+      f32x4 cc[2][kF1];
+      auto reads = [&](int t) {
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        if (t >= nt) break;
+        for (int i = 0; i < kF1; ++i)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) pv[i][h] = Fr::ld_pix(&ux[t * FRB + poff[i] + (4 * h + g) * kFrame * EB]);
+      };
+      auto mmas = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < kF1; ++i) cc[b][i] = Fr::mma(w1[6], pv[i][0], S[i]);
+#pragma unroll
+        for (int i = 0; i < kF1; ++i) cc[b][i] = Fr::mma(w1[7], pv[i][1], cc[b][i]);
+      };
+      auto epi = [&](int t, int b) {
 #pragma unroll
         for (int i = 0; i < kF1; ++i) {
-          f32x4 c0 = S[i];
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            c0 = Fr::mma(w1[6 + h], Fr::ld_pix(&ux[t * FRB + poff[i] + (4 * h + g) * kFrame * EB]), c0);
           const int f = fq + 4 * i;
           if (f >= 25) continue;                          // wave-uniform: store only
           const int p = f * 16 + r16;
-          Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(c0[0] * sc + b1[0], 0.f),
-                  fmaxf(c0[1] * sc + b1[1], 0.f), fmaxf(c0[2] * sc + b1[2], 0.f), fmaxf(c0[3] * sc + b1[3], 0.f),
-                  o8);
+          Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(cc[b][i][0] * sc + b1[0], 0.f),
+                  fmaxf(cc[b][i][1] * sc + b1[1], 0.f), fmaxf(cc[b][i][2] * sc + b1[2], 0.f),
+                  fmaxf(cc[b][i][3] * sc + b1[3], 0.f), o8);
         }
+      };
+      reads(0);
+      mmas(0);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (t + 1 < T) {
+          reads(t + 1);
+          mmas((t + 1) & 1);
+        }
+        epi(t, t & 1);
       }
     }
     lds_barrier();       // x1 complete, frame reads done: conv2's epilogue may overwrite ux
