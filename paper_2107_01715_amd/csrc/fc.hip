@@ -6,13 +6,21 @@
 // A workgroup of 8 wavefronts computes a 256 (stacks) x 256 (neurons) tile:
 // wave (wm, wn) owns 64 x 128, i.e. 4 x 8 MFMA 16x16x32 fragments, so one
 // LDS operand read feeds 4 or 8 MFMAs and each global byte feeds 256 output
-// columns (the L2 -> CU path, not the matrix cores, bounds smaller tiles).  The K
-// loop moves 64 K values per stage: the next stage's tiles are loaded from
-// HBM/L2 into registers while the current stage's MFMAs run, then written to
-// the other half of a double-buffered LDS, so one barrier separates stages.
-// The product is computed transposed (D[neuron][stack] = W X^T) so each lane
-// finishes with 4 consecutive neurons of one stack and stores them at once.
-// Rows past n are clamped (read a valid row) and not stored.
+// columns.  The product is computed transposed (D[neuron][stack] = W X^T) so
+// each lane finishes with 4 consecutive neurons of one stack and stores them
+// at once.  Rows past n are clamped (read a valid row) and not stored.
+//
+// K streams through a ring of 5 LDS stages (64 bytes of every tile row per
+// stage: 32 K values in BF16, 64 in e4m3), filled by direct global->LDS
+// loads (no registers, no LDS store instructions) three stages ahead of the
+// MFMAs.  Such a load writes lane l's 16 bytes at slot l of the
+// instruction's 1 KB window, so the bank-conflict swizzle is applied on the
+// global side: LDS slot (row r, chunk pc) holds the tile's K chunk
+// pc ^ ((r >> 2) & 3), which puts the 16 rows an MFMA operand read touches
+// on distinct banks.  Each stage ends its wavefront's own loads
+// (s_waitcnt vmcnt) before one workgroup barrier; the slot a load refills
+// was last read two stages earlier, before a barrier every wavefront has
+// passed.
 #include "bcts_internal.h"
 
 namespace bcts {
@@ -24,12 +32,26 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 constexpr int kThreads = 512;
-constexpr int kBM = 256, kBN = 256, kBK = 64, kK = 3136;
-constexpr int kStages = kK / kBK;                 // 49
+constexpr int kBM = 256, kBN = 256, kK = 3136;
+constexpr int kRB = 64;                            // bytes of a tile row per stage
+constexpr int kNS = 5;                             // ring stages (5 x 32 KB = the whole LDS)
+constexpr int kAhead = kNS - 2;                    // stages in flight ahead of the MFMAs
+constexpr int kStageBytes = (kBM + kBN) * kRB;
 static_assert(512 / kBN == 2, "the workgroup mapping assumes 2 neuron tiles");
+static_assert(kNS * kStageBytes <= 160 * 1024, "the ring must fit the LDS");
 
 __device__ __forceinline__ void lds_barrier() {
   __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// wait until at most n of this wavefront's vector-memory operations are outstanding
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+    case 0: __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 4: __asm__ volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 8: __asm__ volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    default: __asm__ volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+  }
 }
 
 template <int P> struct FT;
@@ -57,6 +79,9 @@ template <> struct FT<P_FP8> {
   }
 };
 
+// byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B half
+__device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ ((r >> 2) & 3)) << 4); }
+
 template <int P>
 __global__ void __launch_bounds__(kThreads, 1)
 fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char* __restrict__ W,
@@ -64,15 +89,11 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
   typedef FT<P> Ft;
   typedef typename Ft::V V;
   constexpr int EB = Ft::EB;
-  constexpr int RB = kBK * EB;                    // bytes of one tile row per stage
-  constexpr int RS = RB + 16;                     // LDS row stride: +16 B against bank conflicts
-  constexpr int UB = 16;                          // bytes per 16-byte load unit
-  constexpr int UPR = RB / UB;                    // units per row per stage
-  constexpr int AU = kBM * UPR / kThreads;        // A units per thread per stage
-  constexpr int BU = kBN * UPR / kThreads;        // B units per thread per stage
-  constexpr int KS = kBK / 32;                    // MFMA K steps per stage
-  __shared__ __attribute__((aligned(16))) unsigned char As[2][kBM * RS];
-  __shared__ __attribute__((aligned(16))) unsigned char Bs[2][kBN * RS];
+  constexpr int KPS = kRB / EB;                    // K values per stage
+  constexpr int NST = kK / KPS;                    // stages: 98 (BF16), 49 (e4m3)
+  constexpr int KS = KPS / 32;                     // MFMA K steps per stage
+  static_assert(kK % KPS == 0, "K must split into whole stages");
+  __shared__ __attribute__((aligned(1024))) unsigned char ring[kNS][kStageBytes];
 
   // Workgroups are dealt to the 8 XCDs round-robin (XCD = id mod 8), each
   // with its own L2.  The 2 neuron tiles of one stack tile go to the same
@@ -86,36 +107,34 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
   const int n0 = (slot & 1) * kBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int wm = wave >> 1, wn = wave & 1;        // 4 x 2 waves
+  const int wm = wave >> 1, wn = wave & 1;         // 4 x 2 waves
 
-  // global -> register loads of stage st; unit u of a tile = (row u / UPR,
-  // 16-byte column unit u % UPR)
-#define FC1_GLOAD(st)                                                                                   \
-  {                                                                                                     \
-    _Pragma("unroll") for (int i = 0; i < AU; ++i) {                                                    \
-      const int u = tid + i * kThreads, row = u / UPR, cu = u % UPR;                                    \
-      long long m = m0 + row;                                                                           \
-      if (m >= n) m = n - 1;                                                                            \
-      ra[i] = *reinterpret_cast<const uint4*>(X + (m * kK + (long long)(st) * kBK) * EB + cu * UB);     \
-    }                                                                                                   \
-    _Pragma("unroll") for (int i = 0; i < BU; ++i) {                                                    \
-      const int u = tid + i * kThreads, row = u / UPR, cu = u % UPR;                                    \
-      rb[i] = *reinterpret_cast<const uint4*>(W + ((long long)(n0 + row) * kK + (long long)(st) * kBK) * EB + \
-                                              cu * UB);                                                 \
-    }                                                                                                   \
+  // Loads of one stage: 2 instructions for A (X rows) and 2 for B (W rows)
+  // per wavefront; instruction q of a half covers LDS slots [64q, 64q + 64)
+  // of 16 bytes: slot ps = row ps / 4, physical chunk ps % 4.
+  const unsigned char* srcA[2];
+  const unsigned char* srcB[2];
+  int dst[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = wave * 2 + j, ps = q * 64 + lane;
+    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & 3);
+    long long m = m0 + r;
+    if (m >= n) m = n - 1;
+    srcA[j] = X + m * (long long)kK * EB + c * 16;
+    srcB[j] = W + (long long)(n0 + r) * kK * EB + c * 16;
+    dst[j] = q * 1024;                              // wave-uniform LDS window
   }
-#define FC1_LSTORE(buf)                                                                                 \
-  {                                                                                                     \
-    _Pragma("unroll") for (int i = 0; i < AU; ++i) {                                                    \
-      const int u = tid + i * kThreads;                                                                 \
-      *reinterpret_cast<uint4*>(&As[buf][(u / UPR) * RS + (u % UPR) * UB]) = ra[i];                     \
-    }                                                                                                   \
-    _Pragma("unroll") for (int i = 0; i < BU; ++i) {                                                    \
-      const int u = tid + i * kThreads;                                                                 \
-      *reinterpret_cast<uint4*>(&Bs[buf][(u / UPR) * RS + (u % UPR) * UB]) = rb[i];                     \
-    }                                                                                                   \
-  }
-  uint4 ra[AU], rb[BU];
+  auto issue = [&](int st) {
+    unsigned char* base = ring[st % kNS];
+    const long long ko = (long long)st * kRB;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      __builtin_amdgcn_global_load_lds(srcA[j] + ko, (void __attribute__((address_space(3)))*)(base + dst[j]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(srcB[j] + ko, (void __attribute__((address_space(3)))*)(base + kBM * kRB + dst[j]),
+                                       16, 0, 0);
+    }
+  };
 
   f32x4 acc[8][4];            // [neuron frag][stack frag]
 #pragma unroll
@@ -123,31 +142,31 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  FC1_GLOAD(0);
-  FC1_LSTORE(0);
-  lds_barrier();
-  for (int st = 0; st < kStages; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < kStages) FC1_GLOAD(st + 1);
+#pragma unroll
+  for (int st = 0; st < kAhead; ++st) issue(st);
+  for (int st = 0; st < NST; ++st) {
+    if (st + kAhead < NST) issue(st + kAhead);
+    const int later = (NST - 1 - st) < kAhead ? (NST - 1 - st) : kAhead;   // stages issued after st
+    wait_vm(4 * later);
+    lds_barrier();
+    const unsigned char* As = ring[st % kNS];
+    const unsigned char* Bs = As + kBM * kRB;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
+      // this lane's 8 K values of step ks: byte 32 * ks * EB / ... within the row
+      const int kb = ks * 32 * EB + 8 * g * EB;        // byte offset in the row's 64 bytes
+      const int c = kb >> 4, cb = kb & 15;
       V xv[4];
-      const int kb = (ks * 32 + 8 * g) * EB;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        xv[j] = *reinterpret_cast<const V*>(&As[buf][(wm * 64 + j * 16 + r16) * RS + kb]);
+      for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz(wm * 64 + j * 16 + r16, c) + cb);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const V wv = *reinterpret_cast<const V*>(&Bs[buf][(wn * 128 + i * 16 + r16) * RS + kb]);
+        const V wv = *reinterpret_cast<const V*>(Bs + swz(wn * 128 + i * 16 + r16, c) + cb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
       }
     }
-    if (st + 1 < kStages) FC1_LSTORE(buf ^ 1);
-    lds_barrier();
   }
-#undef FC1_GLOAD
-#undef FC1_LSTORE
 
   // epilogue: lane holds neurons n0 + wn*128 + 16i + 4g + q of stack m0 + wm*64 + 16j + r16
 #pragma unroll
