@@ -33,10 +33,12 @@ Two further workloads print their own JSON line:
   --workload beam   pruned search: 64 roots at A=18, depth 4, BF16,
                     exhaustive against beams of 4, 16 and 64 nodes per root
                     action: time per step, leaves scored, and root-action
-                    agreement with the exhaustive search.
+                    agreement with the exhaustive search;
+  --workload copy   a plain 1 GiB device-to-device copy, three times: the
+                    calibration run for the HBM byte counters of a profiler.
 
     python bench.py [--steps K] [--warmup W] [--precision bf16|fp8|fp32]
-                    [--workload headline|mixed|serve|mlp|beam]
+                    [--workload headline|mixed|serve|mlp|beam|copy]
 """
 from __future__ import annotations
 
@@ -102,6 +104,29 @@ def agreement(act, q, ref):
         agree += int(act[r] == ao or act[r] in ties)
     return {"roots": len(ref), "agree": agree, "rate": agree / len(ref),
             "max_rel_err": max(errs), "mean_rel_err": float(np.mean(errs))}
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "conv_fused_bf16_256roots_A18_d3_traffic.md")
+
+
+def measured_traffic(kernel, precision, fused, tuned):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, only for the configuration it was measured on and while the
+    kernel's source is unchanged since (else None)."""
+    import hashlib
+    import re
+    if kernel != "conv_fused" or precision != "bf16" or not fused or tuned.get("round") != 3:
+        return None
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_2107_01715_amd", "csrc", "qnet_fused.hip"), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"source_sha256 qnet_fused.hip:\s*([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != hashlib.sha256(src).hexdigest():
+        return None
+    return int(m.group(1))
 
 
 def _setup(seed, n_roots, budget=0):
@@ -397,6 +422,27 @@ def run_beam(args):
     print(json.dumps(out))
 
 
+def run_copy(args):
+    """Calibration for HBM byte counters: 3 copies of 1 GiB (read 1 GiB,
+    write 1 GiB each)."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms * 1e-3) / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": 3, "warmup": 0, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+                      "data": "synthetic", "config": {"workload": "copy of 1 GiB, 3 times", "bytes": nbytes}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,7 +453,7 @@ def main():
     ap.add_argument("--skip-fp32-single", action="store_true")
     ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
     ap.add_argument("--retune", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp", "beam"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp", "beam", "copy"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--quick", action="store_true",
                     help="headline precision only (no comparison forms, no accuracy): for profiler runs")
@@ -424,6 +470,8 @@ def main():
         return run_mlp(args)
     if args.workload == "beam":
         return run_beam(args)
+    if args.workload == "copy":
+        return run_copy(args)
 
     # CPU baseline first: the worker pool forks before the GPU is touched
     cpu, oracle_ref = (None, {})
@@ -590,10 +638,12 @@ def main():
     exp_ms = kern[0]
     exp_gbs = exp_nodes * EXPAND_BYTES_PER_NODE / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else None
     qnet_tflops = leaves * sum(LAYER_FLOPS.values()) / (kern[1] * 1e-3) / 1e12 if kern[1] > 0 else None
+    traffic = measured_traffic(dom, args.precision, fused, tuned)
     roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision).replace("T", str(tuned.get("round", ""))),
                 "layer": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "flop_per_launch": flops_of[dom] * n_items / max(kern[9], 1),
-                "avg_launch_ms": kernels[dom]["avg_launch_ms"], "traffic": None}
+                "avg_launch_ms": kernels[dom]["avg_launch_ms"], "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
 
     lat = np.array(per_step) if per_step else np.array([ms_step])
     out = {
