@@ -38,7 +38,7 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 constexpr int kThreads = 512;          // 8 wavefronts
-constexpr int kF1 = 7;                 // conv1 pixel fragments per wave: (w>>1) + 4i
+constexpr int kF1 = 4;                 // conv1 pixel fragments per wave: w + 8i
 constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
@@ -231,22 +231,31 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   };
   auto fstage = [&](int slot, const uint4& u) { Fr::stage16(&ux[slot * FRB + ck * 16 * EB], u, s8); };
 
-  // conv1 weights (A operand) of this wave's channel half: K step s covers
-  // stack channel s/2, kernel rows 4(s&1)..+3; lane group g holds kernel row
-  // 4(s&1)+g (8 kw values)
-  V w1[8];
+  // conv1 and the group's S phase map wavefront w to pixel fragments
+  // f = w + 8i (i < kF1; fragment 24 is the last, so only wavefront 0 has an
+  // i = 3) for BOTH channel halves: each pixel operand read from LDS feeds
+  // two MFMAs.  (conv2 / conv3 split channel halves between wavefront pairs.)
+  // conv1 weights (A operand): K step s covers stack channel s/2, kernel rows
+  // 4(s&1)..+3; lane group g holds kernel row 4(s&1)+g (8 kw values).  Only
+  // channel 3 (s = 6, 7) stays in registers; channels 0..2 load for S.
+  auto w1ld = [&](int h2, int s) { return Fr::ld(W1 + ((16 * h2 + r16) * 256 + 32 * s + 8 * g) * EB); };
+  V w1c[2][2];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) w1[s] = Fr::ld(W1 + ((16 * half + r16) * 256 + 32 * s + 8 * g) * EB);
-  float b1[4];
+  for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) b1[q] = a.bias[0][16 * half + 4 * g + q];
+    for (int h = 0; h < 2; ++h) w1c[h2][h] = w1ld(h2, 6 + h);
+  float b1[2][4];
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b1[h2][q] = a.bias[0][16 * h2 + 4 * g + q];
+  const bool f3 = wave == 0;                             // wavefront 0 also owns fragment 24 (i = 3)
 
-  // conv1 pixel fragments f = fq + 4i (fragments past 24 compute a clamped
-  // copy and are not stored): output pixel 16f + r16
+  // output pixel 16f + r16 of conv1 fragment i
   int poff[kF1];
 #pragma unroll
   for (int i = 0; i < kF1; ++i) {
-    const int f = fq + 4 * i;
+    const int f = wave + 8 * i;
     const int p = (f < 25 ? f : 24) * 16 + r16;
     poff[i] = ((p / 20) * 4 * kFrame + (p % 20) * 4) * EB;
   }
@@ -268,17 +277,29 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
     for (int c = 0; c < 3; ++c) fstage(c, sv[c]);
   }
-  lds_barrier();
-  f32x4 S[kF1];
+  f32x4 S[kF1][2];
 #pragma unroll
-  for (int i = 0; i < kF1; ++i) S[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < kF1; ++i) S[i][0] = S[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  {
+    V w1s[2][6];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+    for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
-    for (int i = 0; i < kF1; ++i)
+      for (int s2 = 0; s2 < 6; ++s2) w1s[h2][s2] = w1ld(h2, s2);
+    lds_barrier();
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        S[i] = Fr::mma(w1[2 * c + h], Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]), S[i]);
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < kF1; ++i) {
+        if (i == kF1 - 1 && !f3) continue;               // wave-uniform: fragments past 24
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const V pix = Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]);
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) S[i][h2] = Fr::mma(w1s[h2][2 * c + h], pix, S[i][h2]);
+        }
+      }
+  }
 
   lds_barrier();         // the S reads are done
 #pragma unroll
@@ -294,14 +315,14 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
     // Software-pipelined over the round's items: item t+1's pixel operands
-    // are read and its 14 MFMAs issued before item t's epilogue, so the
+    // are read and its MFMAs issued before item t's epilogue, so the
     // epilogue's VALU work runs while the matrix core is busy.  All T items
     // are computed: a slot past the group's last item holds a staged copy of
     // a valid frame, and its x1 rows are never read by conv2.
     {
       const float sc = a.acc_scale[0], o8 = a.out_s8[0];
       V pv[kF1][2];
-      f32x4 cc[2][kF1];
+      f32x4 cc[2][kF1][2];
       auto reads = [&](int t) {
 #pragma unroll
         for (int i = 0; i < kF1; ++i)
@@ -310,19 +331,24 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       };
       auto mmas = [&](int b) {
 #pragma unroll
-        for (int i = 0; i < kF1; ++i) cc[b][i] = Fr::mma(w1[6], pv[i][0], S[i]);
+        for (int i = 0; i < kF1; ++i)
 #pragma unroll
-        for (int i = 0; i < kF1; ++i) cc[b][i] = Fr::mma(w1[7], pv[i][1], cc[b][i]);
+          for (int h2 = 0; h2 < 2; ++h2) cc[b][i][h2] = Fr::mma(w1c[h2][0], pv[i][0], S[i][h2]);
+#pragma unroll
+        for (int i = 0; i < kF1; ++i)
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) cc[b][i][h2] = Fr::mma(w1c[h2][1], pv[i][1], cc[b][i][h2]);
       };
       auto epi = [&](int t, int b) {
 #pragma unroll
         for (int i = 0; i < kF1; ++i) {
-          const int f = fq + 4 * i;
-          if (f >= 25) continue;                          // wave-uniform: store only
-          const int p = f * 16 + r16;
-          Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * half + 4 * g)], fmaxf(cc[b][i][0] * sc + b1[0], 0.f),
-                  fmaxf(cc[b][i][1] * sc + b1[1], 0.f), fmaxf(cc[b][i][2] * sc + b1[2], 0.f),
-                  fmaxf(cc[b][i][3] * sc + b1[3], 0.f), o8);
+          if (i == kF1 - 1 && !f3) continue;             // wave-uniform: fragments past 24
+          const int p = (wave + 8 * i) * 16 + r16;
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2)
+            Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * h2 + 4 * g)], fmaxf(cc[b][i][h2][0] * sc + b1[h2][0], 0.f),
+                    fmaxf(cc[b][i][h2][1] * sc + b1[h2][1], 0.f), fmaxf(cc[b][i][h2][2] * sc + b1[h2][2], 0.f),
+                    fmaxf(cc[b][i][h2][3] * sc + b1[h2][3], 0.f), o8);
         }
       };
       reads(0);
