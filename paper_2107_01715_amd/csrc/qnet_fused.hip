@@ -232,9 +232,9 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   auto fstage = [&](int slot, const uint4& u) { Fr::stage16(&ux[slot * FRB + ck * 16 * EB], u, s8); };
 
   // conv1 and the group's S phase map wavefront w to pixel fragments
-  // f = w + 8i (i < kF1; fragment 24 is the last, so only wavefront 0 has an
-  // i = 3) for BOTH channel halves: each pixel operand read from LDS feeds
-  // two MFMAs.  (conv2 / conv3 split channel halves between wavefront pairs.)
+  // f = w + 8i (i < 3) and slot i = 3 to fragment 24, for BOTH channel
+  // halves: each pixel operand read from LDS feeds two MFMAs.  (conv2 /
+  // conv3 split channel halves between wavefront pairs.)
   // conv1 weights (A operand): K step s covers stack channel s/2, kernel rows
   // 4(s&1)..+3; lane group g holds kernel row 4(s&1)+g (8 kw values).  Only
   // channel 3 (s = 6, 7) stays in registers; channels 0..2 load for S.
@@ -249,14 +249,17 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
     for (int q = 0; q < 4; ++q) b1[h2][q] = a.bias[0][16 * h2 + 4 * g + q];
-  const bool f3 = wave == 0;                             // wavefront 0 also owns fragment 24 (i = 3)
+  // Fragment 24 (slot i = 3) of a round's item t belongs to wavefront t, so
+  // the round's 25T fragments spread over the wavefronts as evenly as the
+  // per-wave S fragments allow; wavefronts 0..T-1 keep S for fragment 24.
+  const bool f3 = wave < T;
 
   // output pixel 16f + r16 of conv1 fragment i
   int poff[kF1];
 #pragma unroll
   for (int i = 0; i < kF1; ++i) {
-    const int f = wave + 8 * i;
-    const int p = (f < 25 ? f : 24) * 16 + r16;
+    const int f = i == kF1 - 1 ? 24 : wave + 8 * i;
+    const int p = f * 16 + r16;
     poff[i] = ((p / 20) * 4 * kFrame + (p % 20) * 4) * EB;
   }
 
@@ -329,21 +332,27 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
           for (int h = 0; h < 2; ++h) pv[i][h] = Fr::ld_pix(&ux[t * FRB + poff[i] + (4 * h + g) * kFrame * EB]);
       };
-      auto mmas = [&](int b) {
+      auto mmas = [&](int t, int b) {
 #pragma unroll
-        for (int i = 0; i < kF1; ++i)
+        for (int i = 0; i < kF1 - 1; ++i)
 #pragma unroll
           for (int h2 = 0; h2 < 2; ++h2) cc[b][i][h2] = Fr::mma(w1c[h2][0], pv[i][0], S[i][h2]);
 #pragma unroll
-        for (int i = 0; i < kF1; ++i)
+        for (int i = 0; i < kF1 - 1; ++i)
 #pragma unroll
           for (int h2 = 0; h2 < 2; ++h2) cc[b][i][h2] = Fr::mma(w1c[h2][1], pv[i][1], cc[b][i][h2]);
+        if (wave == t) {                                  // wave-uniform: fragment 24 of item t
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) cc[b][3][h2] = Fr::mma(w1c[h2][0], pv[3][0], S[3][h2]);
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) cc[b][3][h2] = Fr::mma(w1c[h2][1], pv[3][1], cc[b][3][h2]);
+        }
       };
       auto epi = [&](int t, int b) {
 #pragma unroll
         for (int i = 0; i < kF1; ++i) {
-          if (i == kF1 - 1 && !f3) continue;             // wave-uniform: fragments past 24
-          const int p = (wave + 8 * i) * 16 + r16;
+          if (i == kF1 - 1 && wave != t) continue;       // wave-uniform: fragment 24 is wave t's
+          const int p = (i == kF1 - 1 ? 24 : wave + 8 * i) * 16 + r16;
 #pragma unroll
           for (int h2 = 0; h2 < 2; ++h2)
             Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * h2 + 4 * g)], fmaxf(cc[b][i][h2][0] * sc + b1[h2][0], 0.f),
@@ -352,12 +361,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         }
       };
       reads(0);
-      mmas(0);
+      mmas(0, 0);
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         if (t + 1 < T) {
           reads(t + 1);
-          mmas((t + 1) & 1);
+          mmas(t + 1, (t + 1) & 1);
         }
         epi(t, t & 1);
       }
