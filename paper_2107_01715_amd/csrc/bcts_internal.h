@@ -98,6 +98,7 @@ struct FusedGroup {
 // Arguments of the fused conv1->conv2->conv3 kernel (BF16 / FP8).
 struct FusedConvArgs {
   const FusedGroup* groups;    // groups of this chunk
+  int n_groups;                // groups in the chunk (the kernel loops over them)
   long long item_base;         // plan-global index of desc[0]
   const ItemDesc* desc;        // chunk-relative item descriptors
   const void* w[3];            // conv weights in operand type: conv1 [N][K], conv2/conv3 fragment-major

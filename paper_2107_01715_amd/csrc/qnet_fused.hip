@@ -42,7 +42,6 @@ constexpr int kF1 = 4;                 // conv1 pixel fragments per wave: w + 8i
 constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
-constexpr int kMaxGroup = 32;          // sibling group size bound (A <= 18)
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -182,12 +181,21 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   constexpr int UXB = (T * L::X2T > NFR * FRB) ? T * L::X2T : NFR * FRB;
   __shared__ __attribute__((aligned(16))) unsigned char x1[T * L::X1T];
   __shared__ __attribute__((aligned(16))) unsigned char ux[UXB];
-  __shared__ const uint8_t* fptr[kMaxGroup];            // channel-3 frame of each item of the group
+  __shared__ __attribute__((aligned(16))) unsigned char w1l[12 * 64 * 8 * EB];   // conv1 weights, channels 0..2
   __shared__ __attribute__((aligned(16))) float sbias[2][64];   // conv2, conv3 biases
 
-  const FusedGroup grp = a.groups[blockIdx.x];
-  const int G = grp.count;
-  const long long i0 = grp.item0 - a.item_base;   // chunk-relative first item
+  // Item descriptors and groups are read-only here: reading them through the
+  // constant address space makes their uniform loads scalar (counted by
+  // lgkmcnt), so waiting for one never waits for the weight loads in flight.
+  typedef const __attribute__((address_space(4))) ItemDesc CDesc;
+  typedef const __attribute__((address_space(4))) FusedGroup CGroup;
+  CDesc* const dsc = (CDesc*)a.desc;
+  CGroup* const grp = (CGroup*)a.groups;
+  // Persistent: workgroup b takes groups b, b + gridDim.x, ... of the chunk.
+  int gi = blockIdx.x;
+  if (gi >= a.n_groups) return;
+  int G = grp[gi].count;
+  long long i0 = grp[gi].item0 - a.item_base;   // chunk-relative first item
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   const int half = wave & 1, fq = wave >> 1;      // channel half, first pixel fragment
@@ -237,8 +245,13 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   // conv3 split channel halves between wavefront pairs.)
   // conv1 weights (A operand): K step s covers stack channel s/2, kernel rows
   // 4(s&1)..+3; lane group g holds kernel row 4(s&1)+g (8 kw values).  Only
-  // channel 3 (s = 6, 7) stays in registers; channels 0..2 load for S.
+  // channel 3 (s = 6, 7) stays in registers; channels 0..2 (used once per
+  // group, by S) are kept in LDS, operand-major: unit (h2, s, lane).
   auto w1ld = [&](int h2, int s) { return Fr::ld(W1 + ((16 * h2 + r16) * 256 + 32 * s + 8 * g) * EB); };
+  for (int k = tid; k < 12 * 64; k += kThreads) {
+    const int hs = k >> 6, l = k & 63, h2 = hs / 6, s2 = hs % 6;
+    *reinterpret_cast<V*>(&w1l[k * 8 * EB]) = Fr::ld(W1 + ((16 * h2 + (l & 15)) * 256 + 32 * s2 + 8 * (l >> 4)) * EB);
+  }
   V w1c[2][2];
 #pragma unroll
   for (int h2 = 0; h2 < 2; ++h2)
@@ -263,50 +276,55 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
     poff[i] = ((p / 20) * 4 * kFrame + (p % 20) * 4) * EB;
   }
 
-  // ---- S: channels 0..2 of the group's shared stack ----
-  // The shared frames and the first round's frames are requested together;
-  // a later round's frames load into registers during the previous round's
-  // conv2/conv3 and are staged at its end.
-  const ItemDesc d0 = a.desc[i0];
-  if (tid < G) fptr[tid] = a.desc[i0 + tid].frame[3];
+  // ---- group inputs ----
+  // The first group's shared frames and first round's frames are requested
+  // here; a later group's arrive in registers during the previous group's
+  // last round (alongside its conv2/conv3) and are staged at that round's
+  // end, so a group starts without an HBM round trip.  A later round's
+  // frames likewise load during the previous round.
   if (tid < 128) sbias[tid >> 6][tid & 63] = a.bias[1 + (tid >> 6)][tid & 63];
-  uint4 fv[T];
-  {
-    uint4 sv[3];
+  uint4 sv[3], fv[T];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sv[c] = fload(d0.frame[c]);
+  for (int c = 0; c < 3; ++c) sv[c] = fload(dsc[i0].frame[c]);
 #pragma unroll
-    for (int t = 0; t < T; ++t) fv[t] = fload(a.desc[i0 + (t < G ? t : G - 1)].frame[3]);
+  for (int t = 0; t < T; ++t) fv[t] = fload(dsc[i0 + (t < G ? t : G - 1)].frame[3]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fstage(c, sv[c]);
-  }
+  for (int c = 0; c < 3; ++c) fstage(c, sv[c]);
+
+  for (;;) {
+  // ---- S: channels 0..2 of the group's shared stack ----
   f32x4 S[kF1][2];
 #pragma unroll
   for (int i = 0; i < kF1; ++i) S[i][0] = S[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-  {
-    V w1s[2][6];
+  lds_barrier();         // the group's shared frames are staged
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V w[2][2];
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
-      for (int s2 = 0; s2 < 6; ++s2) w1s[h2][s2] = w1ld(h2, s2);
-    lds_barrier();
+      for (int h = 0; h < 2; ++h) w[h2][h] = Fr::ld(&w1l[((h2 * 6 + 2 * c + h) * 64 + lane) * 8 * EB]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < kF1; ++i) {
+      if (i == kF1 - 1 && !f3) continue;                 // wave-uniform: fragment 24
 #pragma unroll
-      for (int i = 0; i < kF1; ++i) {
-        if (i == kF1 - 1 && !f3) continue;               // wave-uniform: fragments past 24
+      for (int h = 0; h < 2; ++h) {
+        const V pix = Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const V pix = Fr::ld_pix(&ux[c * FRB + poff[i] + (4 * h + g) * kFrame * EB]);
-#pragma unroll
-          for (int h2 = 0; h2 < 2; ++h2) S[i][h2] = Fr::mma(w1s[h2][2 * c + h], pix, S[i][h2]);
-        }
+        for (int h2 = 0; h2 < 2; ++h2) S[i][h2] = Fr::mma(w[h2][h], pix, S[i][h2]);
       }
+    }
   }
-
   lds_barrier();         // the S reads are done
 #pragma unroll
   for (int t = 0; t < T; ++t) fstage(t, fv[t]);
+
+  // the next group of this workgroup (this group's own when there is none)
+  const int gn = gi + (int)gridDim.x;
+  const bool has_next = gn < a.n_groups;
+  const int gq = __builtin_amdgcn_readfirstlane(has_next ? gn : gi);
+  const int Gq = grp[gq].count;
+  const long long iq = grp[gq].item0 - a.item_base;
 
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
@@ -372,11 +390,23 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       }
     }
     lds_barrier();       // x1 complete, frame reads done: conv2's epilogue may overwrite ux
-    // next round's frames (items past the group load the last item's frame, unused)
+    // The next round's frames; in the group's last round, the next group's
+    // shared frames and first round's frames.  Slots past a group's end load
+    // its last item's frame (staged, never used).
+    const bool last = r0 + T >= G;
+    {
+      const bool nxt = last && has_next;
+      const long long ib = nxt ? iq : i0;
+      const int gb = nxt ? Gq : G, kb = nxt ? 0 : r0 + T;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int k = r0 + T + t;
-      fv[t] = fload(fptr[k < G ? k : G - 1]);
+      for (int t = 0; t < T; ++t) {
+        const int k = kb + t;
+        fv[t] = fload(dsc[ib + (k < gb ? k : gb - 1)].frame[3]);
+      }
+      if (nxt) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[c] = fload(dsc[iq].frame[c]);
+      }
     }
 
     // ---- conv2 (x1 -> x2) and conv3 (x2 -> x3) ----
@@ -497,10 +527,20 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
                   fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
     }
-    lds_barrier();       // conv3's reads of x2 are done: ux takes the next round's frames
+    lds_barrier();       // conv3's reads of x2 are done: ux takes the next frames
+    if (!last) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) fstage(t, fv[t]);
+      for (int t = 0; t < T; ++t) fstage(t, fv[t]);
+    } else if (has_next) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fstage(c, sv[c]);
+    }
     // x1 was last read by conv2, before the barrier after conv2's epilogue
+  }
+  if (!has_next) break;
+  gi = gq;
+  G = Gq;
+  i0 = iq;
   }
 }
 
@@ -526,19 +566,30 @@ void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hip
                      reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), N, K, eb);
 }
 
-void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s) {
+void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups, hipStream_t s) {
   if (n_groups <= 0) return;
-  dim3 grid((unsigned)n_groups), block(kThreads);
+  typedef void (*Kern)(FusedConvArgs);
+  Kern k;
   if (prec == P_BF16) {   // BF16 at T = 4 exceeds the LDS of one CU: T <= 3
-    if (T == 1) hipLaunchKernelGGL((conv_fused_kernel<P_BF16, 1>), grid, block, 0, s, a);
-    else if (T == 2) hipLaunchKernelGGL((conv_fused_kernel<P_BF16, 2>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((conv_fused_kernel<P_BF16, 3>), grid, block, 0, s, a);
+    k = T == 1 ? conv_fused_kernel<P_BF16, 1> : T == 2 ? conv_fused_kernel<P_BF16, 2> : conv_fused_kernel<P_BF16, 3>;
   } else {
-    if (T == 1) hipLaunchKernelGGL((conv_fused_kernel<P_FP8, 1>), grid, block, 0, s, a);
-    else if (T == 2) hipLaunchKernelGGL((conv_fused_kernel<P_FP8, 2>), grid, block, 0, s, a);
-    else if (T == 4) hipLaunchKernelGGL((conv_fused_kernel<P_FP8, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((conv_fused_kernel<P_FP8, 3>), grid, block, 0, s, a);
+    k = T == 1 ? conv_fused_kernel<P_FP8, 1> : T == 2 ? conv_fused_kernel<P_FP8, 2>
+        : T == 4 ? conv_fused_kernel<P_FP8, 4> : conv_fused_kernel<P_FP8, 3>;
   }
+  // one workgroup per resident slot (all CUs, at the kernel's occupancy);
+  // each loops over the groups b, b + grid, ...
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kThreads, 0) !=
+          hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  const long long slots = (long long)ncu * per_cu;
+  FusedConvArgs a = args;
+  a.n_groups = n_groups;
+  const unsigned grid = (unsigned)(n_groups < slots ? n_groups : slots);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), 0, s, a);
 }
 
 }  // namespace bcts
