@@ -16,8 +16,12 @@
 // MFMAs.  Such a load writes lane l's 16 bytes at slot l of the
 // instruction's 1 KB window, so the bank-conflict swizzle is applied on the
 // global side: LDS slot (row r, chunk pc) holds the tile's K chunk
-// pc ^ ((r >> 2) & 3), which puts the 16 rows an MFMA operand read touches
-// on distinct banks.  Each stage ends its wavefront's own loads
+// pc ^ ((r >> 2) & 2).  A 16-byte LDS read serves each 32-lane half of a
+// wavefront in two cycles, one per parity of lane bits 2, 3 and 4, and a
+// cycle is conflict-free when its 16 lanes touch 16 distinct 16-byte bank
+// groups (64 banks of 4 bytes); for an operand read (lane = 16 x chunk
+// group + row) this swizzle gives every cycle 16 distinct groups, where a
+// plain or (r >> 2) & 3 layout gives 8.  Each stage ends its wavefront's own loads
 // (s_waitcnt vmcnt) before one workgroup barrier; the slot a load refills
 // was last read two stages earlier, before a barrier every wavefront has
 // passed.
@@ -80,7 +84,7 @@ template <> struct FT<P_FP8> {
 };
 
 // byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B half
-__device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ ((r >> 2) & 3)) << 4); }
+__device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ ((r >> 2) & 2)) << 4); }
 
 template <int P>
 __global__ void __launch_bounds__(kThreads, 1)
@@ -118,7 +122,7 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = wave * 2 + j, ps = q * 64 + lane;
-    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & 3);
+    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & 2);
     long long m = m0 + r;
     if (m >= n) m = n - 1;
     srcA[j] = X + m * (long long)kK * EB + c * 16;
