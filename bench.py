@@ -110,9 +110,11 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "conv_fused_bf16_256roots_A18_d
 
 
 def measured_traffic(kernel, precision, fused, tuned):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, only for the configuration it was measured on and while the
-    kernel's source is unchanged since (else None)."""
+    """HBM bytes per stack of the dominant kernel from the committed counter
+    summary, only for the kernel and round size it was measured on and while
+    the kernel's source is unchanged since (else None).  The per-stack figure
+    does not depend on how the stacks are chunked into launches (measured at
+    two chunk sizes)."""
     import hashlib
     import re
     if kernel != "conv_fused" or precision != "bf16" or not fused or tuned.get("round") != 3:
@@ -122,11 +124,11 @@ def measured_traffic(kernel, precision, fused, tuned):
         src = open(os.path.join(ROOT, "paper_2107_01715_amd", "csrc", "qnet_fused.hip"), "rb").read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m = re.search(r"traffic_bytes_per_stack:\s*([0-9.]+)", text)
     h = re.search(r"source_sha256 qnet_fused.hip:\s*([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != hashlib.sha256(src).hexdigest():
         return None
-    return int(m.group(1))
+    return float(m.group(1))
 
 
 def _setup(seed, n_roots, budget=0):
@@ -638,7 +640,8 @@ def main():
     exp_ms = kern[0]
     exp_gbs = exp_nodes * EXPAND_BYTES_PER_NODE / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else None
     qnet_tflops = leaves * sum(LAYER_FLOPS.values()) / (kern[1] * 1e-3) / 1e12 if kern[1] > 0 else None
-    traffic = measured_traffic(dom, args.precision, fused, tuned)
+    per_stack = measured_traffic(dom, args.precision, fused, tuned)
+    traffic = per_stack * n_items / max(kern[9], 1) if per_stack is not None else None
     roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision).replace("T", str(tuned.get("round", ""))),
                 "layer": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "flop_per_launch": flops_of[dom] * n_items / max(kern[9], 1),

@@ -1,6 +1,7 @@
 // Fused convolution stack of the Nature-DQN (conv1 -> conv2 -> conv3) for
-// BF16 / FP8 operands on the CDNA4 matrix cores, one workgroup per sibling
-// group of eval items.
+// BF16 / FP8 operands on the CDNA4 matrix cores.  Work comes in sibling
+// groups of eval items; the kernel is persistent: one workgroup per resident
+// slot loops over groups b, b + gridDim.x, ...
 //
 // Siblings (the A children of one node, or the A depth-1 nodes of a root)
 // share stack channels 0..2: a child's stack is its parent's last three
@@ -13,20 +14,21 @@
 //
 // Data path of a workgroup (8 wavefronts):
 //   * a frame is read from HBM once, converted to the operand type once and
-//     staged in LDS (double-buffered; the next item's frame is loaded into
-//     registers while the current one is used);
+//     staged in LDS; the next round's frames (in a group's last round, the
+//     next group's) load into registers during conv2/conv3 and are staged at
+//     the end of the round;
 //   * conv1 -> x1 (20x20x32) and conv2 -> x2 (9x9x64) of T items at a time
-//     stay in LDS, in swizzled layouts that keep the MFMA operand reads free
-//     of bank conflicts without padding;
+//     stay in LDS (layouts below);
 //   * conv3 -> x3 (7x7x64, channels-last) goes to HBM for fc1.
 // Every layer is an implicit GEMM computed transposed, D[channel][pixel] =
 // W[channel][k] * X[k][pixel], with 16x16x32 MFMAs (BF16 or OCP e4m3, FP32
 // accumulate): the weights are the A operand and the im2col pixels the B
 // operand, so each lane ends with 4 consecutive channels of one pixel and
 // stores them with one 8-byte (BF16) or 4-byte (FP8) write.  A wavefront owns
-// a set of 16-pixel fragments and half the channel fragments of a layer.  The sum
-// order of every output element is fixed by the layer, never by the group
-// size, round size or chunking, so results do not depend on batching.
+// a set of 16-pixel fragments and, in conv2 / conv3, half the channel
+// fragments (in conv1 both halves).  The sum order of every output element
+// is fixed by the layer, never by the group size, round size or chunking, so
+// results do not depend on batching.
 #include "bcts_internal.h"
 
 namespace bcts {
@@ -138,10 +140,14 @@ template <> struct F<P_FP8> {
   }
 };
 
-// LDS layouts (byte offsets), padded so that the MFMA operand reads of 8
-// consecutive lanes (b128, BF16) or 16 lanes (b64, FP8) hit distinct banks,
-// and arranged so that every K step of a lane reads at a compile-time offset
-// from one per-fragment base address.
+// LDS layouts (byte offsets), arranged so that every K step of a lane reads
+// at a compile-time offset from one per-fragment base address, and padded to
+// spread the operand reads over the banks.  (gfx950 serves a 16-byte read of
+// each 32-lane half-wavefront in two cycles, one per parity of lane bits
+// 2^3^4, each needing 16 distinct 16-byte bank groups; under that rule
+// conv2's reads of x1 take about twice the conflict-free cycles, which
+// measurements put off the kernel's critical path: the conv2/conv3 weight
+// stream is.)
 //  x1: conv1 output 20x20x32 split into the 4 stride-2 phases (y&1, x&1) of
 //      10x10 pixels each; pixel stride 40 elements (32 channels + 8 pad).
 //      conv2's input pixel (2oy+kh, 2ox+kw) is then pixel (oy + kh/2,
@@ -162,10 +168,9 @@ template <int P> struct Lay {
 };
 
 // One workgroup of 8 wavefronts per CU (the rounds use most of the LDS), so
-// two wavefronts share each SIMD and cover each other's memory latency.
-// Wavefronts work in pairs: wave w takes channel half (w & 1) of every layer
-// and pixel fragments (w >> 1) + 4i.  conv2/conv3 weight fragments stream
-// from L2 two K steps ahead.
+// two wavefronts share each SIMD and cover each other's memory latency.  In
+// conv2 / conv3 wave w takes channel half (w & 1) and pixel fragments
+// (w >> 1) + 4i; their weight fragments stream from L2 kD K steps ahead.
 template <int P, int T>
 __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
   typedef F<P> Fr;
