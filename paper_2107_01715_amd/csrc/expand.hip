@@ -233,7 +233,10 @@ expand_kernel(int k, long long n_nodes, LevelRoots lr, const RootInfo* __restric
       v.y = pix4(m255 >> 4, m128 >> 4);
       v.z = pix4(m255 >> 8, m128 >> 8);
       v.w = pix4(m255 >> 12, m128 >> 12);
-      *reinterpret_cast<uint4*>(frames + (g0 + b) * kFrameBytes + o) = v;
+      // streaming store: frames are written once and read by a later kernel,
+      // far more of them than the caches hold
+      typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+      __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4*>(frames + (g0 + b) * kFrameBytes + o));
     }
     __syncthreads();
   }
