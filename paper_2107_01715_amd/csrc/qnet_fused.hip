@@ -31,6 +31,8 @@
 // results do not depend on batching.
 #include "bcts_internal.h"
 
+#include <atomic>
+
 namespace bcts {
 namespace {
 
@@ -574,23 +576,33 @@ void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hip
 void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups, hipStream_t s) {
   if (n_groups <= 0) return;
   typedef void (*Kern)(FusedConvArgs);
+  // BF16 at T = 4 exceeds the LDS of one CU: T <= 3; other values take 3
+  const int Tk = (T == 1 || T == 2 || (T == 4 && prec != P_BF16)) ? T : 3;
   Kern k;
-  if (prec == P_BF16) {   // BF16 at T = 4 exceeds the LDS of one CU: T <= 3
-    k = T == 1 ? conv_fused_kernel<P_BF16, 1> : T == 2 ? conv_fused_kernel<P_BF16, 2> : conv_fused_kernel<P_BF16, 3>;
+  if (prec == P_BF16) {
+    k = Tk == 1 ? conv_fused_kernel<P_BF16, 1> : Tk == 2 ? conv_fused_kernel<P_BF16, 2> : conv_fused_kernel<P_BF16, 3>;
   } else {
-    k = T == 1 ? conv_fused_kernel<P_FP8, 1> : T == 2 ? conv_fused_kernel<P_FP8, 2>
-        : T == 4 ? conv_fused_kernel<P_FP8, 4> : conv_fused_kernel<P_FP8, 3>;
+    k = Tk == 1 ? conv_fused_kernel<P_FP8, 1> : Tk == 2 ? conv_fused_kernel<P_FP8, 2>
+        : Tk == 4 ? conv_fused_kernel<P_FP8, 4> : conv_fused_kernel<P_FP8, 3>;
   }
   // one workgroup per resident slot (all CUs, at the kernel's occupancy);
-  // each loops over the groups b, b + grid, ...
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-    ncu = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kThreads, 0) !=
-          hipSuccess || per_cu <= 0)
-    per_cu = 1;
-  const long long slots = (long long)ncu * per_cu;
+  // each loops over the groups b, b + grid, ...  The slot count of a
+  // (device, kernel) pair is queried once and cached.
+  constexpr int kDevs = 64;
+  static std::atomic<int> slot_cache[kDevs][2][5];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  std::atomic<int>* cached = dev < kDevs ? &slot_cache[dev][prec == P_BF16 ? 0 : 1][Tk] : nullptr;
+  int slots = cached ? cached->load(std::memory_order_relaxed) : 0;
+  if (slots <= 0) {
+    int ncu = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kThreads, 0) !=
+            hipSuccess || per_cu <= 0)
+      per_cu = 1;
+    slots = ncu * per_cu;
+    if (cached) cached->store(slots, std::memory_order_relaxed);
+  }
   FusedConvArgs a = args;
   a.n_groups = n_groups;
   const unsigned grid = (unsigned)(n_groups < slots ? n_groups : slots);
