@@ -215,6 +215,12 @@ bcts_status bcts_progress(bcts_ctx* ctx, int32_t* pending);
 bcts_status bcts_poll(bcts_ctx* ctx, uint64_t ticket, int32_t* action, float* q, double* t_done);
 /* Serving limits: max requests per engine batch, max batches in flight.   */
 bcts_status bcts_serve_config(bcts_ctx* ctx, int32_t max_batch, int32_t max_inflight);
+/* While requests are queued or batches are in flight (finished results
+ * waiting for bcts_poll do not count), the calls that change what those
+ * batches read -- bcts_set_env, bcts_set_qnet, bcts_set_precision,
+ * bcts_set_fp8_scales, bcts_calibrate_fp8, bcts_set_tuning, bcts_set_beam,
+ * bcts_autotune -- return BCTS_E_STATE and change nothing; drive
+ * bcts_progress until it reports nothing pending first.                    */
 /* Device bytes one request of (depth, A) reserves while admitted.         */
 size_t bcts_request_bytes(int32_t depth, int32_t A);
 

@@ -816,6 +816,19 @@ struct ServeEngine {
   }
 };
 
+// Serving work that reads the context's model, tables and settings: queued
+// requests and batches in flight (finished results waiting for bcts_poll do
+// not count).  The calls that change that state refuse while it exists.
+static bcts_status refuse_if_serving(bcts_ctx* c, const char* what) {
+  if (!c->serve) return BCTS_OK;
+  bcts_status st = c->serve->retire();
+  if (st != BCTS_OK) return st;
+  bool busy = !c->serve->queue.empty();
+  for (const auto& sl : c->serve->slots) busy = busy || sl.busy;
+  if (busy) return fail(c, BCTS_E_STATE, "%s: serving requests are queued or in flight", what);
+  return BCTS_OK;
+}
+
 // ===========================================================================
 extern "C" {
 
@@ -833,9 +846,13 @@ bcts_status bcts_create(int hip_device, size_t hbm_budget_bytes, bcts_ctx** out)
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete c; return BCTS_E_HIP; }
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
-  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return BCTS_E_HIP; }
-  for (int i = 0; i < 4; ++i)
-    if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return BCTS_E_HIP; }
+  bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < 4 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+  if (!ok) {                          // release what was created
+    (void)hipGetLastError();
+    bcts_destroy(c);
+    return BCTS_E_HIP;
+  }
   *out = c;
   return BCTS_OK;
 }
@@ -875,6 +892,7 @@ bcts_status bcts_reset(bcts_ctx* c) {
 bcts_status bcts_set_env(bcts_ctx* c, const bcts_env_params* env) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_env")) != BCTS_OK) return st;
   if (!env) return fail(c, BCTS_E_INVAL, "env is NULL");
   for (int a = 0; a < kMaxA; ++a)
     for (int k = 0; k < 2; ++k)
@@ -893,6 +911,7 @@ bcts_status bcts_set_env(bcts_ctx* c, const bcts_env_params* env) {
 bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_qnet")) != BCTS_OK) return st;
   if (!blob) return fail(c, BCTS_E_INVAL, "blob is NULL");
   if (n_floats != (size_t)BCTS_QNET_NUMEL)
     return fail(c, BCTS_E_INVAL, "blob has %zu floats, expected %d", n_floats, BCTS_QNET_NUMEL);
@@ -984,6 +1003,7 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
 bcts_status bcts_set_precision(bcts_ctx* c, bcts_precision prec) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_precision")) != BCTS_OK) return st;
   if (prec != BCTS_FP32 && prec != BCTS_BF16 && prec != BCTS_FP8)
     return fail(c, BCTS_E_INVAL, "unknown precision %d", (int)prec);
   c->prec = (int)prec;
@@ -999,6 +1019,7 @@ bcts_status bcts_get_fp8_scales(bcts_ctx* c, float* out5) {
 bcts_status bcts_set_fp8_scales(bcts_ctx* c, const float* in5) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_fp8_scales")) != BCTS_OK) return st;
   if (!in5) return fail(c, BCTS_E_INVAL, "scales are NULL");
   for (int l = 0; l < 5; ++l)
     if (!(in5[l] > 0.f) || !std::isfinite(in5[l])) return fail(c, BCTS_E_INVAL, "scale %d not positive", l);
@@ -1010,6 +1031,7 @@ bcts_status bcts_set_fp8_scales(bcts_ctx* c, const float* in5) {
 bcts_status bcts_calibrate_fp8(bcts_ctx* c, int32_t n, const uint8_t* stacks) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_calibrate_fp8")) != BCTS_OK) return st;
   if (n <= 0 || !stacks) return fail(c, BCTS_E_INVAL, "need n > 0 calibration stacks");
   if (!c->qnet_set) return fail(c, BCTS_E_STATE, "no Q-network set");
   HIPCHECK(c, hipSetDevice(c->device));
@@ -1305,6 +1327,7 @@ bcts_status bcts_poll(bcts_ctx* c, uint64_t ticket, int32_t* action, float* q, d
 bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_tuning")) != BCTS_OK) return st;
   switch (key) {
     case BCTS_TUNE_FUSED:
       c->fused = value != 0;
@@ -1343,6 +1366,7 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
                           int64_t* out_best) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_autotune")) != BCTS_OK) return st;
   if (reps < 1 || !out_best) return fail(c, BCTS_E_INVAL, "reps >= 1 and out_best required");
   // candidates: fused on/off (FP32 is never fused), round T, fused chunk size
   const int Ts[4] = {1, 2, 3, 4};
@@ -1355,7 +1379,10 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0));
-  HIPCHECK(c, hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, BCTS_E_HIP, "hipEventCreate failed");
+  }
   c->timing = false;
   for (int fz = (c->prec == P_FP32 ? 0 : 1); fz >= 0 && st == BCTS_OK; --fz) {
     for (int ti = 0; ti < (fz ? 4 : 1) && st == BCTS_OK; ++ti) {
@@ -1413,6 +1440,7 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
 bcts_status bcts_set_beam(bcts_ctx* c, int32_t beam) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if ((st = refuse_if_serving(c, "bcts_set_beam")) != BCTS_OK) return st;
   if (beam < 0 || beam > kMaxBeam) return fail(c, BCTS_E_INVAL, "beam=%d outside [0,%d]", beam, kMaxBeam);
   c->beam = beam;
   return BCTS_OK;

@@ -90,3 +90,34 @@ def test_admission_under_small_budget(lib):
         ctx.poll(123456789, 4)
     assert e.value.status == lib.E_STATE
     ctx.close()
+
+
+def test_settings_refused_while_serving(lib):
+    """Calls that change what queued or running batches read are refused
+    with E_STATE until the engine has nothing pending; finished results that
+    are not polled yet do not block them, and keep the values they were
+    computed with."""
+    ctx = make_ctx(lib, prec=lib.BF16)
+    ctx.serve_config(2, 1)
+    corr = lib.correction(True, 1.0)
+    n = 24
+    pos, st = W.roots(78, n)
+    tickets = [ctx.submit(pos[i], st[i], 3, 18, GAMMA, corr) for i in range(n)]
+    assert ctx.progress() > 0       # 12 batches of 5,832-leaf searches, one at a time
+    for call in (lambda: ctx.set_precision(lib.FP32), lambda: ctx.set_beam(2),
+                 lambda: ctx.set_tuning(lib.TUNE_FUSED_ROUND, 2),
+                 lambda: ctx.set_qnet(W.qnet_blob(W.qnet_weights(8)))):
+        with pytest.raises(lib.BctsError) as e:
+            call()
+        assert e.value.status == lib.E_STATE
+    t0 = time.time()
+    while ctx.progress() > 0:
+        assert time.time() - t0 < 60.0, "serving did not finish"
+    ctx.set_precision(lib.FP32)     # nothing pending: allowed before polling
+    res = drain(ctx, tickets, [18] * n)
+    ctx.set_precision(lib.BF16)
+    for i in (0, n - 1):
+        a1, q1 = ctx.search(pos[i:i + 1], st[i:i + 1], 3, 18, GAMMA, corr)
+        assert res[tickets[i]][0] == a1[0]
+        np.testing.assert_array_equal(res[tickets[i]][1], q1[0])
+    ctx.close()
