@@ -284,3 +284,39 @@ def test_fused_rounds_and_chunks_are_bitwise_identical(lib, setup, prec_name, ro
     ctx.set_tuning(lib.TUNE_FUSED_ROUND, 3)
     ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 262144)
     ctx.set_precision(lib.FP32)
+
+
+@pytest.mark.parametrize("prec_name,T", [("BF16", 3), ("FP8", 4)])
+def test_persistent_loop_over_mixed_groups(lib, setup, prec_name, T):
+    """The fused kernel's workgroups loop over sibling groups (prefetching
+    the next group's frames) when a launch holds more groups than there are
+    resident workgroups.  300 roots of mixed A and depth give groups of 1, 4,
+    6 and 18 stacks in one launch; the results must equal, bit for bit, the
+    launches of a few groups each (no workgroup loops), and sampled roots
+    meet the operand-precision bound against the oracle."""
+    ctx, world, _ = setup
+    n = 300
+    pos, st = W.roots(1006, n)
+    A, d = W.mixed_shapes(1006, n, (4, 6, 18), (1, 2))
+    corr = lib.correction(True, 1.0)
+    if prec_name == "FP8":
+        _, cal = W.roots(2003, 64)
+        ctx.calibrate_fp8(cal)
+    ctx.set_precision(getattr(lib, prec_name))
+    ctx.set_tuning(lib.TUNE_FUSED, 1)
+    ctx.set_tuning(lib.TUNE_FUSED_ROUND, T)
+    try:
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 1048576)
+        a1, q1 = ctx.search_batch(pos, st, d, A, GAMMA, corr)
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 37)
+        a2, q2 = ctx.search_batch(pos, st, d, A, GAMMA, corr)
+    finally:
+        ctx.set_tuning(lib.TUNE_FUSED_ROUND, 3)
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 262144)
+        ctx.set_precision(lib.FP32)
+    assert np.array_equal(a1, a2) and np.array_equal(q1, q2)
+    if prec_name == "BF16":
+        for r in (0, 151, 299):
+            ref = S.search(world, pos[r], st[r], int(d[r]), int(A[r]), GAMMA, correction=True, c=1.0)
+            rel = np.abs(q1[r, :A[r]].astype(np.float64) - np.asarray(ref.q)).max() / np.abs(ref.q).max()
+            assert rel < 2e-2, (r, rel)
