@@ -88,8 +88,10 @@ def test_c1_end_to_end(lib, setup, corr_on, c):
         assert_root_parity(q[r], act[r], ref, 4, f"root {r}")
 
 
-@pytest.mark.parametrize("A,d", [(4, 0), (6, 0), (4, 1), (18, 1), (6, 3), (3, 4), (2, 2)])
+@pytest.mark.parametrize("A,d", [(4, 0), (6, 0), (4, 1), (18, 1), (18, 2), (6, 3), (3, 4), (2, 2), (2, 5), (2, 6)])
 def test_shapes_end_to_end(lib, setup, A, d):
+    """FP32 end to end over the shape range: depth 0 (no search), the
+    largest A (18) and the largest depth (6)."""
     ctx, world, _ = setup
     ctx.set_precision(lib.FP32)
     pos, st = W.roots(1002 + A + d, 4)
