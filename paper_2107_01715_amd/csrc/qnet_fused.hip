@@ -335,10 +335,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
-    // the first kD weight steps of conv2 load while conv1 runs
-    V wr[kRing][2];
-#pragma unroll
-    for (int u = 0; u < kD; ++u) wstep(u, wr[u % kRing]);
+    V wr[kRing][2];      // conv2 / conv3 weight ring (its first kD steps load during conv1)
     lds_barrier();       // the round's frames are staged
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
@@ -385,13 +382,24 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
                     fmaxf(cc[b][i][h2][3] * sc + b1[h2][3], 0.f), o8);
         }
       };
+      // The first kD K steps of conv2's weights are requested in T parts,
+      // each after an item's MFMAs: issued all at once they wait on the
+      // vector-memory path (8 wavefronts x 2 KB per step), which conv1 does
+      // not otherwise use, so spread out they overlap conv1's work.
+      auto ring_part = [&](int j) {
+#pragma unroll
+        for (int u = j * kD / T; u < (j + 1) * kD / T; ++u) wstep(u, wr[u % kRing]);
+        __builtin_amdgcn_sched_barrier(0);
+      };
       reads(0);
       mmas(0, 0);
+      ring_part(0);
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         if (t + 1 < T) {
           reads(t + 1);
           mmas(t + 1, (t + 1) & 1);
+          ring_part(t + 1);
         }
         epi(t, t & 1);
       }
