@@ -11,7 +11,9 @@ The FP64 oracle needs about 0.2 s per root here, so it checks sampled roots:
 and over all 256 roots, properties that hold at any size:
 * BF16 root actions agree with the FP32 path on >= 99.5% of the roots;
 * BF16 results are bit-identical when the stacks are chunked differently.
-The empty batch is an argument error.
+The empty batch is an argument error.  Beyond the headline, two roots at
+A = 18 and depth 4 check the BF16 path against the FP32 one (the oracle is
+too slow at that size) and against itself under another chunking.
 """
 import numpy as np
 import pytest
@@ -103,3 +105,28 @@ def test_empty_batch_is_rejected(lib, headline):
         ctx.search(pos[:0], st[:0], D, A, GAMMA, lib.correction(True, 1.0))
     assert e.value.status == lib.E_INVAL
     ctx.search(pos, st, 1, A, GAMMA, lib.correction(True, 1.0))      # the context stays usable
+
+
+def test_largest_tree_a18_depth4(lib, headline):
+    """A = 18 at depth 4 (104,976 leaves per root, the deepest tree of the
+    configurations' range; the FP64 oracle needs minutes per root there):
+    BF16 agrees with the FP32 GPU path within the BF16 operand error, and is
+    bit-identical when its stacks are chunked differently."""
+    ctx = headline[0]
+    pos, st = W.roots(INSTANCE_SEED + 1, 2)
+    corr = lib.correction(True, 1.0)
+    ctx.set_precision(lib.FP32)
+    a32, q32 = ctx.search(pos, st, 4, A, GAMMA, corr)
+    ctx.set_precision(lib.BF16)
+    try:
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 1048576)
+        a1, q1 = ctx.search(pos, st, 4, A, GAMMA, corr)
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 65536)
+        a2, q2 = ctx.search(pos, st, 4, A, GAMMA, corr)
+    finally:
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 1048576)
+        ctx.set_precision(lib.FP32)
+    assert np.array_equal(a1, a2) and np.array_equal(q1, q2)
+    rel = np.abs(q1.astype(np.float64) - q32).max(axis=1) / np.abs(q32).max(axis=1)
+    print(f"A=18 d=4 BF16 vs FP32: rel err {np.round(rel, 5)}")
+    assert rel.max() < 2e-2, rel
