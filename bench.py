@@ -119,13 +119,15 @@ def measured_traffic(kernel, precision, fused, tuned):
     import re
     if kernel != "conv_fused" or precision != "bf16" or not fused or tuned.get("round") != 3:
         return None
+    csrc = os.path.join(ROOT, "paper_2107_01715_amd", "csrc")
     try:
         text = open(TRAFFIC_PROFILE).read()
-        src = open(os.path.join(ROOT, "paper_2107_01715_amd", "csrc", "qnet_fused.hip"), "rb").read()
+        # the kernel and the header that fixes its output layout
+        src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("qnet_fused.hip", "bcts_internal.h"))
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_stack:\s*([0-9.]+)", text)
-    h = re.search(r"source_sha256 qnet_fused.hip:\s*([0-9a-f]{64})", text)
+    h = re.search(r"source_sha256 qnet_fused.hip\+bcts_internal.h:\s*([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != hashlib.sha256(src).hexdigest():
         return None
     return float(m.group(1))

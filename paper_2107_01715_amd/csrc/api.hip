@@ -65,10 +65,15 @@ void gev_coeffs(int A, int d, double* pe, double* po) {
   *po = gev_bias(no) / std::sqrt(2.0);
 }
 
-// fused path: x3 [chunk][3136] and h [chunk][512] in the operand type
+// fused path: x3 [chunk rounded up to fc1's 256-row tiles][3136] and
+// h [chunk][512] in the operand type
+size_t fused_x3_bytes(long long chunk, int prec) {
+  const size_t el = prec == P_BF16 ? 2 : 1;
+  return align_up((size_t)(fc1_padded_rows(chunk) / kFc1Rows) * (size_t)fc1_tile_bytes((int)el));
+}
 size_t fused_workspace_bytes(long long chunk, int prec) {
   const size_t el = prec == P_BF16 ? 2 : 1;
-  return (size_t)chunk * 3136 * el + 256 + (size_t)chunk * 512 * el + 256;
+  return fused_x3_bytes(chunk, prec) + (size_t)chunk * 512 * el + 256;
 }
 
 double now_s() {
@@ -446,9 +451,8 @@ bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameB
     }
     fa.acc_scale[0] /= 255.f;
     fa.pix_s8 = f8 ? q.ascale[0] : 1.f;
-    const size_t el = f8 ? 1 : 2;
     char* x3 = A + p.o_ws;
-    char* h = x3 + align_up((size_t)p.chunk * 3136 * el);
+    char* h = x3 + fused_x3_bytes(p.chunk, c->prec);
     fa.x3 = x3;
     if (cev) HIPCHECK(c, hipEventRecord(cev[0], s));
     launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s);
@@ -950,7 +954,8 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
   std::memcpy(B[3].data(), f1b, sizeof(float) * 512);
   std::memcpy(B[4].data(), f2b, sizeof(float) * 18);
 
-  // fp32 w, bf16 w, fp8 w, bias, and for conv2 / conv3 fragment-major bf16 and fp8 copies
+  // fp32 w, bf16 w, fp8 w, bias, and for conv2 / conv3 fragment-major (fc1: stage-major tiled)
+  // bf16 and fp8 copies
   size_t off[5][6], o = 0;
   for (int l = 0; l < 5; ++l) {
     const size_t n = W[l].size();
@@ -958,8 +963,9 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
     off[l][1] = o; o += align_up(n * 2);
     off[l][2] = o; o += align_up(n);
     off[l][3] = o; o += align_up(B[l].size() * 4);
-    off[l][4] = o; o += (l == 1 || l == 2) ? align_up(n * 2) : 0;
-    off[l][5] = o; o += (l == 1 || l == 2) ? align_up(n) : 0;
+    const size_t fc1_tiles = (size_t)(NK[3][0] / kFc1Rows);
+    off[l][4] = o; o += (l == 1 || l == 2) ? align_up(n * 2) : l == 3 ? align_up(fc1_tiles * fc1_tile_bytes(2)) : 0;
+    off[l][5] = o; o += (l == 1 || l == 2) ? align_up(n) : l == 3 ? align_up(fc1_tiles * fc1_tile_bytes(1)) : 0;
   }
   if (c->wmem) {
     HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -989,6 +995,11 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
       c->q.wf8[l] = base + off[l][5];
       launch_fragment_major(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, c->stream);
       launch_fragment_major(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, c->stream);
+    } else if (l == 3) {
+      c->q.wfb[l] = base + off[l][4];
+      c->q.wf8[l] = base + off[l][5];
+      launch_fc1_weight_tiles(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, c->stream);
+      launch_fc1_weight_tiles(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, c->stream);
     }
   }
   // activation scales until calibrated: pixels 1:1 (255 -> 256 in e4m3), others unit

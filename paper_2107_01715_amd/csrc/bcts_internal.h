@@ -30,6 +30,21 @@ constexpr int kSprites = 8;
 constexpr int kMaxA = 18;
 constexpr int kMaxD = 6;
 
+// fc1's operands (its input x3 [rows][3136] and its weights [512][3136], in
+// the operand type of eb bytes per element) are stored in stage-major tiles:
+// rows in tiles of 256, and in a tile each 64-byte K slice of all 256 rows is
+// one contiguous 16 KB block, the block fc1 streams per stage.  Byte kb of
+// row r lives at fc1_tiled_offset(r, kb, eb).  Row counts are padded to a
+// multiple of 256 (fc1 reads the padding rows and stores nothing for them).
+constexpr int kFc1Rows = 256;
+constexpr int kFc1K = 3136;
+constexpr int kFc1StageBytes = kFc1Rows * 64;
+__host__ __device__ inline long long fc1_tile_bytes(int eb) { return (long long)(kFc1K * eb / 64) * kFc1StageBytes; }
+__host__ __device__ inline long long fc1_tiled_offset(long long r, int kb, int eb) {
+  return (r / kFc1Rows) * fc1_tile_bytes(eb) + (long long)(kb >> 6) * kFc1StageBytes + (r % kFc1Rows) * 64 + (kb & 63);
+}
+inline long long fc1_padded_rows(long long n) { return (n + kFc1Rows - 1) / kFc1Rows * kFc1Rows; }
+
 // Per-root descriptor (device resident).
 struct RootInfo {
   int A, d;
@@ -106,7 +121,7 @@ struct FusedConvArgs {
   float acc_scale[3];          // accumulator scale (1/255 on conv1; fp8 operand scales)
   float out_s8[3];             // fp8: input scale of the next layer
   float pix_s8;                // fp8: pixel scale
-  void* x3;                    // out: [chunk items][49][64] channels-last
+  void* x3;                    // out: [chunk items][49][64] channels-last, in fc1's stage-major tiles
 };
 void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s);
 
@@ -123,7 +138,8 @@ struct QnetDev {
   float wscale[5];             // fp8 weight scale: w8 = e4m3(w * wscale)
   float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
   // conv2 / conv3 (index 1, 2) in fragment-major order for the fused kernel:
-  // unit (cf, s, lane) = the 8 operand elements W[16cf + lane%16][32s + 8(lane/16) ..]
+  // unit (cf, s, lane) = the 8 operand elements W[16cf + lane%16][32s + 8(lane/16) ..];
+  // fc1 (index 3) in stage-major tiles for fc1_kernel
   const void* wfb[5];          // bf16
   const void* wf8[5];          // e4m3
 };
@@ -145,13 +161,19 @@ void launch_mlp_root(const MlpDev& m, int n, int d, const float* states, const f
 // Copies W[N][K] (element size eb bytes) into fragment-major order.
 void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hipStream_t s);
 
-// fc1 as a 256 x 128-tiled MFMA GEMM (BF16 / FP8): h = ReLU(acc_scale *
-// x3 W^T + b) in the operand type (FP8 outputs scaled by out_s8).
+// Copies fc1's W[N][K] (N a multiple of 256, eb bytes per element) into
+// stage-major tiles.
+void launch_fc1_weight_tiles(const void* src, void* dst, int N, int K, int eb, hipStream_t s);
+
+// fc1 as a 256 x 256-tiled MFMA GEMM (BF16 / FP8): h = ReLU(acc_scale *
+// x3 W^T + b) in the operand type (FP8 outputs scaled by out_s8); x3 and w
+// in stage-major tiles (x3 padded to a multiple of 256 rows), h [n][512].
 void launch_fc1_mfma(int prec, long long n, const void* x3, const void* w, const float* bias, float acc_scale,
                      float out_s8, void* h, hipStream_t s);
 
 // fc1 (+ReLU) and fc2 (+max over A, root rows of Q_0) over a chunk whose
-// conv3 output x3 is ready; `h` holds [n][512] in the operand type.
+// conv3 output x3 is ready (BF16 / FP8, from the fused kernel, in fc1's
+// stage-major tiles); `h` holds [n][512] in the operand type.
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
                     const void* x3, void* h, float* V, float* q0, hipStream_t s,
                     hipEvent_t ev_after_fc1 = nullptr);

@@ -493,8 +493,8 @@ void run_fc(const QnetDev& q, const ItemDesc* desc, long long n, const void* x3,
   a.desc = desc;
   a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3);
   a.out_s8 = P == P_FP8 ? q.ascale[4] : 1.f; a.out = h;
-  if (P == P_FP32) run_layer<3, P>(a, s);
-  else launch_fc1_mfma(P, n, x3, wp(3), q.b[3], accs(3), a.out_s8, h, s);
+  static_assert(P != P_FP32, "x3 comes from the fused kernel (BF16 / FP8), in stage-major tiles");
+  launch_fc1_mfma(P, n, x3, P == P_BF16 ? q.wfb[3] : q.wf8[3], q.b[3], accs(3), a.out_s8, h, s);
   if (ev) (void)hipEventRecord(ev, s);
   a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
   run_layer<4, P>(a, s);
@@ -542,8 +542,7 @@ void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n, 
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h,
                     float* V, float* q0, hipStream_t s, hipEvent_t ev) {
   if (n <= 0) return;
-  if (prec == P_FP32) run_fc<P_FP32>(q, desc, n, x3, h, V, q0, s, ev);
-  else if (prec == P_BF16) run_fc<P_BF16>(q, desc, n, x3, h, V, q0, s, ev);
+  if (prec == P_BF16) run_fc<P_BF16>(q, desc, n, x3, h, V, q0, s, ev);
   else run_fc<P_FP8>(q, desc, n, x3, h, V, q0, s, ev);
 }
 

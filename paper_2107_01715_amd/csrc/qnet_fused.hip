@@ -19,7 +19,8 @@
 //     the end of the round;
 //   * conv1 -> x1 (20x20x32) and conv2 -> x2 (9x9x64) of T items at a time
 //     stay in LDS (layouts below);
-//   * conv3 -> x3 (7x7x64, channels-last) goes to HBM for fc1.
+//   * conv3 -> x3 (7x7x64, channels-last) goes to HBM for fc1, in fc1's
+//     stage-major tiles (a 4- or 8-byte store stays inside one 64-byte slice).
 // Every layer is an implicit GEMM computed transposed, D[channel][pixel] =
 // W[channel][k] * X[k][pixel], with 16x16x32 MFMAs (BF16 or OCP e4m3, FP32
 // accumulate): the weights are the A operand and the im2col pixels the B
@@ -534,10 +535,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       for (int i = 0; i < F3W; ++i) {
         if (!ok[i]) continue;
         const int r = (fq + 4 * i) * 16 + r16;
-        const long long row = (item_first + pt[i]) * 49 + (r - pt[i] * 49);
+        const long long item = item_first + pt[i];
+        const int px = r - pt[i] * 49;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          Fr::st4(X3 + (row * 64 + 32 * half + 16 * j + 4 * g) * EB, fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
+          Fr::st4(X3 + fc1_tiled_offset(item, (px * 64 + 32 * half + 16 * j + 4 * g) * EB, EB),
+                  fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
                   fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
                   fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
       }
