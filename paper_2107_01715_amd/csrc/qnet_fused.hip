@@ -25,7 +25,9 @@
 // W[channel][k] * X[k][pixel], with 16x16x32 MFMAs (BF16 or OCP e4m3, FP32
 // accumulate): the weights are the A operand and the im2col pixels the B
 // operand, so each lane ends with 4 consecutive channels of one pixel and
-// stores them with one 8-byte (BF16) or 4-byte (FP8) write.  A wavefront owns
+// stores them with one 8-byte (BF16) or 4-byte (FP8) write.  conv3's weight
+// rows are paired (launch_fragment_major) so that a lane's two channel
+// fragments hold 8 consecutive channels: one 16-byte or 8-byte write each.  A wavefront owns
 // a set of 16-pixel fragments and, in conv2 / conv3, half the channel
 // fragments (in conv1 both halves).  The sum order of every output element
 // is fixed by the layer, never by the group size, round size or chunking, so
@@ -114,6 +116,14 @@ template <> struct F<P_BF16> {
   __device__ static void st4(void* p, float a, float b, float c, float d, float) {
     *reinterpret_cast<uint2*>(p) = make_uint2(bf2_pack(a, b), bf2_pack(c, d));
   }
+  // 8 consecutive channels as two packed halves of 4 -> 16 bytes
+  typedef uint2 PK;
+  __device__ static PK pk4(float a, float b, float c, float d, float) {
+    return make_uint2(bf2_pack(a, b), bf2_pack(c, d));
+  }
+  __device__ static void st8(void* p, PK lo, PK hi) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+  }
 };
 template <> struct F<P_FP8> {
   typedef uint8_t E;
@@ -141,6 +151,11 @@ template <> struct F<P_FP8> {
   __device__ static void st4(void* p, float a, float b, float c, float d, float s8) {
     *reinterpret_cast<unsigned*>(p) = fp8_pack4(a * s8, b * s8, c * s8, d * s8);
   }
+  typedef unsigned PK;
+  __device__ static PK pk4(float a, float b, float c, float d, float s8) {
+    return fp8_pack4(a * s8, b * s8, c * s8, d * s8);
+  }
+  __device__ static void st8(void* p, PK lo, PK hi) { *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi); }
 };
 
 // LDS layouts (byte offsets), arranged so that every K step of a lane reads
@@ -529,7 +544,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[1][32 * half + 16 * j + 4 * g + q];
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[1][32 * half + 8 * g + 4 * j + q];   // permuted rows
       const long long item_first = i0 + r0;
 #pragma unroll
       for (int i = 0; i < F3W; ++i) {
@@ -537,12 +552,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         const int r = (fq + 4 * i) * 16 + r16;
         const long long item = item_first + pt[i];
         const int px = r - pt[i] * 49;
+        typename Fr::PK pk[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          Fr::st4(X3 + fc1_tiled_offset(item, (px * 64 + 32 * half + 16 * j + 4 * g) * EB, EB),
-                  fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
-                  fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
-                  fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+          pk[j] = Fr::pk4(fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f), fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f),
+                          fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f), fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+        Fr::st8(X3 + fc1_tiled_offset(item, (px * 64 + 32 * half + 8 * g) * EB, EB), pk[0], pk[1]);
       }
     }
     lds_barrier();       // conv3's reads of x2 are done: ux takes the next frames
@@ -563,25 +578,31 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 }
 
 // Fragment-major copy of W[N][K]: unit u = (cf, s, lane) receives the 8
-// elements W[16cf + lane%16][32s + 8(lane/16) .. +7].
+// elements W[row][32s + 8(lane/16) .. +7] of row 16cf + lane%16, or with
+// `pair8` of row 32(cf/2) + 8(l/4) + 4(cf%2) + l%4 (l = lane%16): then the
+// two fragments 2h, 2h + 1 leave lane group g of an MFMA result with the 8
+// consecutive channels 32h + 8g .. +7.
 __global__ void fragment_major_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int N,
-                                      int K, int eb) {
+                                      int K, int eb, int pair8) {
   const int NS = K / 32;
   const long long units = (long long)(N / 16) * NS * 64;
   const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= units) return;
   const int lane = (int)(u % 64), s = (int)((u / 64) % NS), cf = (int)(u / 64 / NS);
-  const unsigned char* sp = src + ((long long)(16 * cf + lane % 16) * K + 32 * s + 8 * (lane / 16)) * eb;
+  const int l = lane % 16;
+  const int row = pair8 ? 32 * (cf / 2) + 8 * (l / 4) + 4 * (cf % 2) + l % 4 : 16 * cf + l;
+  const unsigned char* sp = src + ((long long)row * K + 32 * s + 8 * (lane / 16)) * eb;
   unsigned char* dp = dst + u * 8 * eb;
   for (int b = 0; b < 8 * eb; ++b) dp[b] = sp[b];
 }
 
 }  // namespace
 
-void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, hipStream_t s) {
+void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, bool pair8, hipStream_t s) {
   const long long units = (long long)(N / 16) * (K / 32) * 64;
   hipLaunchKernelGGL(fragment_major_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), N, K, eb);
+                     reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), N, K, eb,
+                     pair8 ? 1 : 0);
 }
 
 void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups, hipStream_t s) {
