@@ -993,8 +993,8 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
     if (l == 1 || l == 2) {
       c->q.wfb[l] = base + off[l][4];
       c->q.wf8[l] = base + off[l][5];
-      launch_fragment_major(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, l == 2, c->stream);
-      launch_fragment_major(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, l == 2, c->stream);
+      launch_fragment_major(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, true, c->stream);
+      launch_fragment_major(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, true, c->stream);
     } else if (l == 3) {
       c->q.wfb[l] = base + off[l][4];
       c->q.wf8[l] = base + off[l][5];

@@ -139,7 +139,7 @@ struct QnetDev {
   float ascale[5];             // fp8 input scale of each layer: x8 = e4m3(x * ascale)
   // conv2 / conv3 (index 1, 2) in fragment-major order for the fused kernel:
   // unit (cf, s, lane) = the 8 operand elements W[16cf + lane%16][32s + 8(lane/16) ..]
-  // (conv3: rows paired, see launch_fragment_major);
+  // (rows paired, see launch_fragment_major);
   // fc1 (index 3) in stage-major tiles for fc1_kernel
   const void* wfb[5];          // bf16
   const void* wf8[5];          // e4m3
@@ -160,7 +160,7 @@ void launch_mlp_root(const MlpDev& m, int n, int d, const float* states, const f
                      int32_t* act, float* q, hipStream_t s);
 
 // Copies W[N][K] (element size eb bytes) into fragment-major order; with
-// pair8 (conv3, N = 64) the rows of channel fragments 2h, 2h + 1 are
+// pair8 (conv2, conv3: N = 64) the rows of channel fragments 2h, 2h + 1 are
 // interleaved in groups of 4 so each lane group's results are 8 consecutive
 // channels.
 void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, bool pair8, hipStream_t s);

@@ -25,9 +25,11 @@
 // W[channel][k] * X[k][pixel], with 16x16x32 MFMAs (BF16 or OCP e4m3, FP32
 // accumulate): the weights are the A operand and the im2col pixels the B
 // operand, so each lane ends with 4 consecutive channels of one pixel and
-// stores them with one 8-byte (BF16) or 4-byte (FP8) write.  conv3's weight
-// rows are paired (launch_fragment_major) so that a lane's two channel
-// fragments hold 8 consecutive channels: one 16-byte or 8-byte write each.  A wavefront owns
+// stores them with one 8-byte (BF16) or 4-byte (FP8) write.  conv2's and
+// conv3's weight rows are paired (launch_fragment_major) so that a lane's
+// two channel fragments hold 8 consecutive channels: one 16-byte or 8-byte
+// write each (x2's pixel stride, 9 x 16 bytes in BF16, keeps any 8
+// consecutive lanes of such a write on distinct bank groups).  A wavefront owns
 // a set of 16-pixel fragments and, in conv2 / conv3, half the channel
 // fragments (in conv1 both halves).  The sum order of every output element
 // is fixed by the layer, never by the group size, round size or chunking, so
@@ -487,17 +489,18 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[0][32 * half + 16 * j + 4 * g + q];
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[0][32 * half + 8 * g + 4 * j + q];   // paired rows
 #pragma unroll
       for (int i = 0; i < F2W; ++i) {
         if (!ok[i]) continue;
         const int r = (fq + 4 * i) * 16 + r16;
         const int t = r / 81, p = r % 81;
+        typename Fr::PK pk[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          Fr::st4(&ux[L::x2(t, p, 32 * half + 16 * j + 4 * g)], fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f),
-                  fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f), fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f),
-                  fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+          pk[j] = Fr::pk4(fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f), fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f),
+                          fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f), fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+        Fr::st8(&ux[L::x2(t, p, 32 * half + 8 * g)], pk[0], pk[1]);
       }
     }
     lds_barrier();
