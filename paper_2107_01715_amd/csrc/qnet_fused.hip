@@ -24,12 +24,13 @@
 // Every layer is an implicit GEMM computed transposed, D[channel][pixel] =
 // W[channel][k] * X[k][pixel], with 16x16x32 MFMAs (BF16 or OCP e4m3, FP32
 // accumulate): the weights are the A operand and the im2col pixels the B
-// operand, so each lane ends with 4 consecutive channels of one pixel and
-// stores them with one 8-byte (BF16) or 4-byte (FP8) write.  conv2's and
-// conv3's weight rows are paired (launch_fragment_major) so that a lane's
-// two channel fragments hold 8 consecutive channels: one 16-byte or 8-byte
-// write each (x2's pixel stride, 9 x 16 bytes in BF16, keeps any 8
-// consecutive lanes of such a write on distinct bank groups).  A wavefront owns
+// operand, so each lane ends with 4 consecutive channels of one pixel per
+// channel fragment.  The weight rows of every layer are paired (conv1 at its
+// loads, conv2 / conv3 in launch_fragment_major) so that a lane's two channel
+// fragments hold 8 consecutive channels, stored with one 16-byte (BF16) or
+// 8-byte (FP8) write; the pixel strides of x1 (5 x 16 bytes, its x phases
+// 8000 bytes apart) and x2 (9 x 16 bytes) keep any 8 consecutive lanes of
+// such a write on distinct LDS bank groups.  A wavefront owns
 // a set of 16-pixel fragments and, in conv2 / conv3, half the channel
 // fragments (in conv1 both halves).  The sum order of every output element
 // is fixed by the layer, never by the group size, round size or chunking, so
@@ -272,10 +273,14 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   // 4(s&1)..+3; lane group g holds kernel row 4(s&1)+g (8 kw values).  Only
   // channel 3 (s = 6, 7) stays in registers; channels 0..2 (used once per
   // group, by S) are kept in LDS, operand-major: unit (h2, s, lane).
-  auto w1ld = [&](int h2, int s) { return Fr::ld(W1 + ((16 * h2 + r16) * 256 + 32 * s + 8 * g) * EB); };
+  // Row l of channel fragment h2 is channel 8(l/4) + 4 h2 + l%4 (paired
+  // rows), so lane group g's results of both fragments are the 8
+  // consecutive channels 8g .. 8g + 7, stored with one write.
+  auto w1row = [](int h2, int l) { return 8 * (l >> 2) + 4 * h2 + (l & 3); };
+  auto w1ld = [&](int h2, int s) { return Fr::ld(W1 + (w1row(h2, r16) * 256 + 32 * s + 8 * g) * EB); };
   for (int k = tid; k < 12 * 64; k += kThreads) {
     const int hs = k >> 6, l = k & 63, h2 = hs / 6, s2 = hs % 6;
-    *reinterpret_cast<V*>(&w1l[k * 8 * EB]) = Fr::ld(W1 + ((16 * h2 + (l & 15)) * 256 + 32 * s2 + 8 * (l >> 4)) * EB);
+    *reinterpret_cast<V*>(&w1l[k * 8 * EB]) = Fr::ld(W1 + (w1row(h2, l & 15) * 256 + 32 * s2 + 8 * (l >> 4)) * EB);
   }
   V w1c[2][2];
 #pragma unroll
@@ -286,7 +291,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
 #pragma unroll
   for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) b1[h2][q] = a.bias[0][16 * h2 + 4 * g + q];
+    for (int q = 0; q < 4; ++q) b1[h2][q] = a.bias[0][8 * g + 4 * h2 + q];
   // Fragment 24 (slot i = 3) of a round's item t belongs to wavefront t, so
   // the round's 25T fragments spread over the wavefronts as evenly as the
   // per-wave S fragments allow; wavefronts 0..T-1 keep S for fragment 24.
@@ -393,11 +398,13 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         for (int i = 0; i < kF1; ++i) {
           if (i == kF1 - 1 && wave != t) continue;       // wave-uniform: fragment 24 is wave t's
           const int p = (i == kF1 - 1 ? 24 : wave + 8 * i) * 16 + r16;
+          typename Fr::PK pk[2];
 #pragma unroll
           for (int h2 = 0; h2 < 2; ++h2)
-            Fr::st4(&x1[L::x1(t, p / 20, p % 20, 16 * h2 + 4 * g)], fmaxf(cc[b][i][h2][0] * sc + b1[h2][0], 0.f),
-                    fmaxf(cc[b][i][h2][1] * sc + b1[h2][1], 0.f), fmaxf(cc[b][i][h2][2] * sc + b1[h2][2], 0.f),
-                    fmaxf(cc[b][i][h2][3] * sc + b1[h2][3], 0.f), o8);
+            pk[h2] = Fr::pk4(fmaxf(cc[b][i][h2][0] * sc + b1[h2][0], 0.f), fmaxf(cc[b][i][h2][1] * sc + b1[h2][1], 0.f),
+                             fmaxf(cc[b][i][h2][2] * sc + b1[h2][2], 0.f), fmaxf(cc[b][i][h2][3] * sc + b1[h2][3], 0.f),
+                             o8);
+          Fr::st8(&x1[L::x1(t, p / 20, p % 20, 8 * g)], pk[0], pk[1]);
         }
       };
       // The first kD K steps of conv2's weights are requested in T parts,
