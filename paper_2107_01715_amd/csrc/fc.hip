@@ -76,6 +76,14 @@ template <> struct FT<P_BF16> {
     const bf16x2 h1 = __builtin_convertvector(f32x2{c, d}, bf16x2);
     *reinterpret_cast<uint2*>(p) = make_uint2(__builtin_bit_cast(unsigned, h0), __builtin_bit_cast(unsigned, h1));
   }
+  // 8 consecutive neurons -> 16 bytes
+  __device__ static void st8(void* p, const float (&v)[8], float) {
+    unsigned w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      w[k] = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{v[2 * k], v[2 * k + 1]}, bf16x2));
+    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 };
 template <> struct FT<P_FP8> {
   typedef long V;
@@ -88,6 +96,18 @@ template <> struct FT<P_FP8> {
     d = fminf(fmaxf(d * s8, -448.f), 448.f);
     const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
     *reinterpret_cast<unsigned*>(p) = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
+  }
+  __device__ static void st8(void* p, const float (&v)[8], float s8) {
+    unsigned w[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = fminf(fmaxf(v[4 * k + q] * s8, -448.f), 448.f);
+      const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+      w[k] = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], lo, true);
+    }
+    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
   }
 };
 
@@ -179,18 +199,27 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
     }
   }
 
-  // epilogue: lane holds neurons n0 + wn*128 + 16i + 4g + q of stack m0 + wm*64 + 16j + r16
+  // epilogue: the weight rows are paired (fc1_weight_tiles_kernel), so
+  // fragments 2k and 2k + 1 give the lane neurons n0 + wn*128 + 32k + 8g
+  // + 0..7 of stack m0 + wm*64 + 16j + r16: one 16-byte (BF16) or 8-byte
+  // (FP8) store
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int nb = n0 + wn * 128 + 16 * i + 4 * g;
-    const float b0 = bias[nb], b1 = bias[nb + 1], b2 = bias[nb + 2], b3 = bias[nb + 3];
+  for (int k = 0; k < 4; ++k) {
+    const int nb = n0 + wn * 128 + 32 * k + 8 * g;
+    float b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = bias[nb + e];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long m = m0 + wm * 64 + 16 * j + r16;
-      if (m < n)
-        Ft::st4(H + (m * 512 + nb) * EB, fmaxf(acc[i][j][0] * acc_scale + b0, 0.f),
-                fmaxf(acc[i][j][1] * acc_scale + b1, 0.f), fmaxf(acc[i][j][2] * acc_scale + b2, 0.f),
-                fmaxf(acc[i][j][3] * acc_scale + b3, 0.f), out_s8);
+      if (m < n) {
+        float v[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[4 * h + q] = fmaxf(acc[2 * k + h][j][q] * acc_scale + b[4 * h + q], 0.f);
+        Ft::st8(H + (m * 512 + nb) * EB, v, out_s8);
+      }
     }
   }
 }
@@ -203,8 +232,12 @@ __global__ void fc1_weight_tiles_kernel(const unsigned char* __restrict__ src, u
   if (u >= N * per_row) return;
   const long long r = u / per_row;
   const int kb = (int)(u % per_row) * 16;
+  // row rho of fragment 2k + h (tile rows 32k .. 32k + 31) holds neuron
+  // 32k + 8 (rho / 4) + 4h + rho % 4
+  const int w = (int)(r & 31), h = w >> 4, rho = w & 15;
+  const long long sr = (r & ~31LL) + 8 * (rho >> 2) + 4 * h + (rho & 3);
   *reinterpret_cast<uint4*>(dst + fc1_tiled_offset(r, kb, eb)) =
-      *reinterpret_cast<const uint4*>(src + r * K * eb + kb);
+      *reinterpret_cast<const uint4*>(src + sr * K * eb + kb);
 }
 
 }  // namespace
