@@ -131,9 +131,17 @@ struct bcts_ctx {
   // arena
   char* arena = nullptr;
   size_t arena_bytes = 0;
-  // pinned staging for tables and host I/O
+  // pinned staging for host I/O
   char* pinned = nullptr;
   size_t pinned_bytes = 0;
+  // two pinned staging buffers for the plan tables, used in turn: a search
+  // fills one while the copy of the previous search's tables from the other
+  // may still be queued; tpin_ev[b] marks the end of buffer b's last copy
+  char* tpin[2] = {nullptr, nullptr};
+  size_t tpin_bytes[2] = {0, 0};
+  hipEvent_t tpin_ev[2] = {nullptr, nullptr};
+  bool tpin_busy[2] = {false, false};
+  int tpin_next = 0;
   // timing: events of the last timed search (see collect_timing)
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -399,11 +407,31 @@ bcts_status upload_tables_at(bcts_ctx* c, const Plan& p, char* arena, char* h, h
   return BCTS_OK;
 }
 
+// The tables go through the staging buffer not used by the previous search,
+// after waiting for that buffer's own last copy only: the host plans and
+// stages a search while the previous one still runs.  The device copy is
+// ordered on `s` after the previous search's kernels, which read the tables.
 bcts_status upload_tables(bcts_ctx* c, const Plan& p, hipStream_t s) {
-  bcts_status st = ensure_pinned(c, p.table_bytes);
+  const int b = c->tpin_next;
+  if (c->tpin_busy[b]) {
+    HIPCHECK(c, hipEventSynchronize(c->tpin_ev[b]));
+    c->tpin_busy[b] = false;
+  }
+  if (c->tpin_bytes[b] < p.table_bytes) {
+    if (c->tpin[b]) HIPCHECK(c, hipHostFree(c->tpin[b]));
+    c->tpin[b] = nullptr;
+    c->tpin_bytes[b] = 0;
+    const size_t nb = std::max(p.table_bytes, (size_t)1 << 20);
+    HIPCHECK(c, hipHostMalloc((void**)&c->tpin[b], nb, hipHostMallocDefault));
+    c->tpin_bytes[b] = nb;
+  }
+  if (!c->tpin_ev[b]) HIPCHECK(c, hipEventCreateWithFlags(&c->tpin_ev[b], hipEventDisableTiming));
+  const bcts_status st = upload_tables_at(c, p, c->arena, c->tpin[b], s);
   if (st != BCTS_OK) return st;
-  HIPCHECK(c, hipStreamSynchronize(s));     // staging may still feed an earlier copy
-  return upload_tables_at(c, p, c->arena, c->pinned, s);
+  HIPCHECK(c, hipEventRecord(c->tpin_ev[b], s));
+  c->tpin_busy[b] = true;
+  c->tpin_next = b ^ 1;
+  return BCTS_OK;
 }
 
 // Enqueue the kernels of a planned search.  Root inputs and outputs are
@@ -870,6 +898,11 @@ void bcts_destroy(bcts_ctx* c) {
   if (c->wmem) (void)hipFree(c->wmem);
   if (c->mlp_mem) (void)hipFree(c->mlp_mem);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int b = 0; b < 2; ++b) {
+    if (c->tpin_ev[b]) (void)hipEventSynchronize(c->tpin_ev[b]);
+    if (c->tpin_ev[b]) (void)hipEventDestroy(c->tpin_ev[b]);
+    if (c->tpin[b]) (void)hipHostFree(c->tpin[b]);
+  }
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
