@@ -180,12 +180,22 @@ bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_
  *   BCTS_TUNE_FUSED_ROUND  stacks per LDS round of the fused kernel: 1..4
  *                          (BF16 caps at 3: a round of 4 exceeds the LDS)
  *   BCTS_TUNE_FUSED_CHUNK  stacks per Q-network chunk on the fused path
- *   BCTS_TUNE_LAYER_CHUNK  stacks per chunk on the layer-by-layer path    */
+ *   BCTS_TUNE_LAYER_CHUNK  stacks per chunk on the layer-by-layer path
+ *                          (also the FP32 correction evaluations below)
+ *   BCTS_TUNE_CORR_FP32    1 = (default) the Q-network inputs of the
+ *                          correction -- Q(s_0, .), which fixes pi_o, and the
+ *                          depth-1 values of the Bellman errors (Prop. 3.6)
+ *                          -- are evaluated in FP32 whatever the precision,
+ *                          so that a low-precision rounding cannot flip pi_o
+ *                          or move delta; the leaves (and depth-0 searches)
+ *                          keep the search precision.  0 = every evaluation
+ *                          at the search precision.                         */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
   BCTS_TUNE_FUSED_CHUNK = 2,
-  BCTS_TUNE_LAYER_CHUNK = 3
+  BCTS_TUNE_LAYER_CHUNK = 3,
+  BCTS_TUNE_CORR_FP32 = 4
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);
@@ -279,6 +289,14 @@ bcts_status bcts_debug_expand(bcts_ctx* ctx, const int32_t* pos, const uint8_t* 
 /* Q-network on n host stacks at the current precision: out_q float [n][A]. */
 bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
                             float* out_q);
+/* The same with the stacks in sibling groups of `group` (1..18) consecutive
+ * stacks (the last group may be shorter), the grouping a search gives the A
+ * children of one node (Alg. 1: a child's stack is its parent's last three
+ * frames plus its own): the stacks of a group must share channels 0..2
+ * (BCTS_E_INVAL otherwise).  The fused BF16/FP8 kernel then computes the
+ * shared channels' part of conv1 once per group, as in a search.           */
+bcts_status bcts_debug_qnet_siblings(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
+                                     int32_t group, float* out_q);
 /* Kernel timing with HIP events on the search's own stream.  While enabled,
  * every search (host, device or graph form) records events around its
  * launches and waits for them; bcts_get_timing then reports the last search:
@@ -286,7 +304,9 @@ bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int
  *   out[3] whole search ms, out[4..8] conv1/conv2/conv3/fc1/fc2 ms summed over
  *   chunks, out[9] chunks (launches per layer), out[10..15] expansion ms of
  *   levels 1..6, out[16] Q-network items, out[17] expanded nodes, out[18] 1 if
- *   the fused conv kernel ran (its time is then in out[4]; out[5..6] are 0).
+ *   the fused conv kernel ran (its time is then in out[4]; out[5..6] are 0),
+ *   out[19] ms of the FP32 correction evaluations (BCTS_TUNE_CORR_FP32;
+ *   included in out[1], not in out[4..8]).
  * A graph replay fills only out[3] (ms per replay).  out has 24 doubles.    */
 bcts_status bcts_set_timing(bcts_ctx* ctx, int32_t enabled);
 bcts_status bcts_get_timing(bcts_ctx* ctx, double* out24);

@@ -29,18 +29,53 @@ def relu(x: np.ndarray) -> np.ndarray:
     return np.maximum(x, 0.0)
 
 
+def _round_mantissa(y: np.ndarray, keep: int) -> np.ndarray:
+    """Round float32 values to `keep` explicit mantissa bits, nearest even,
+    on their bit patterns: add half a unit of the kept last place (minus one,
+    plus the kept last bit, which makes exact halves go to even) and clear
+    the dropped bits.  Finite inputs only."""
+    drop = 23 - keep
+    u = np.ascontiguousarray(y, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = u + ((1 << (drop - 1)) - 1) + ((u >> drop) & 1)
+    u = u & ~np.uint64((1 << drop) - 1)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def round_bf16(x: np.ndarray) -> np.ndarray:
-    """Round to bfloat16 (nearest even) and back; torch's conversion."""
-    import torch
-    return torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).double().numpy()
+    """Round to bfloat16 (8 significant bits, nearest even) and back: the
+    float32 value first, then its mantissa to 7 explicit bits."""
+    return _round_mantissa(np.asarray(x, dtype=np.float32), 7)
 
 
 def round_e4m3(x: np.ndarray) -> np.ndarray:
-    """Saturate to +-448 and round to OCP FP8 e4m3 (nearest even) and back;
-    torch's float8_e4m3fn conversion."""
-    import torch
+    """Saturate to +-448 and round to OCP FP8 e4m3 (nearest even) and back:
+    normal values (|x| >= 2^-6) keep 3 explicit mantissa bits; below that
+    the grid is uniform with spacing 2^-9 (subnormals)."""
     y = np.clip(np.asarray(x, dtype=np.float64), -448.0, 448.0).astype(np.float32)
-    return torch.from_numpy(y).to(torch.float8_e4m3fn).double().numpy()
+    normal = _round_mantissa(y, 3)
+    sub = np.rint(y.astype(np.float64) * 512.0) / 512.0        # rint: nearest even
+    return np.where(np.abs(y) >= 2.0 ** -6, normal, sub)
+
+
+_LOWP_W: dict = {}
+
+
+def _rounded_weights(w: dict, name: str, prec: str):
+    """The rounded weight operand of a layer (and, for fp8, its scale),
+    computed once per weight dict (the dict is kept alive by the cache)."""
+    rnd = round_bf16 if prec == "bf16" else round_e4m3
+    key = (id(w), name, prec, id(rnd))
+    hit = _LOWP_W.get(key)
+    if hit is not None and hit[0] is w and hit[3] is rnd:
+        return hit[1], hit[2]
+    W = w[name + ".w"]
+    if prec == "bf16":
+        Wq, ws = round_bf16(W), 1.0
+    else:
+        ws = 448.0 / float(np.abs(W).max())
+        Wq = round_e4m3(W * ws)
+    _LOWP_W[key] = (w, Wq, ws, rnd)
+    return Wq, ws
 
 
 def qvalues_lowp(stacks: np.ndarray, w: dict, A: int, prec: str, ascale=None) -> np.ndarray:
@@ -59,19 +94,18 @@ def qvalues_lowp(stacks: np.ndarray, w: dict, A: int, prec: str, ascale=None) ->
     layers = (("conv1", 4), ("conv2", 2), ("conv3", 1), ("fc1", 0), ("fc2", 0))
     x = s.astype(np.float64)                     # raw pixels
     for l, (name, stride) in enumerate(layers):
-        W = w[name + ".w"]
         b = w[name + ".b"]
-        if name == "fc2":
-            W, b = W[:A], b[:A]
         if prec == "bf16":
-            xq, Wq, div = round_bf16(x), round_bf16(W), 1.0
+            Wq, _ = _rounded_weights(w, name, prec)
+            xq, div = round_bf16(x), 1.0
         elif prec == "fp8":
-            ws = 448.0 / float(np.abs(w[name + ".w"]).max())
+            Wq, ws = _rounded_weights(w, name, prec)
             xq = round_e4m3(x * float(ascale[l]))
-            Wq = round_e4m3(W * ws)
             div = float(ascale[l]) * ws
         else:
             raise ValueError(prec)
+        if name == "fc2":
+            Wq, b = Wq[:A], b[:A]
         if l == 0:
             div *= 255.0
         if stride:

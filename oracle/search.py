@@ -46,34 +46,36 @@ class World:
     w64: dict           # FP64 Q-network weights (qnet.prepare)
 
 
-def qmax(world: World, stacks: np.ndarray, A: int) -> np.ndarray:
-    """max_a Q(s, a) for a batch of stacks."""
-    return Q.qvalues(stacks, world.w64, A).max(axis=1)
+def qmax(world: World, stacks: np.ndarray, A: int, qfn=None) -> np.ndarray:
+    """max_a Q(s, a) for a batch of stacks; `qfn(stacks, A)` replaces the
+    FP64 network (e.g. by its low-precision emulation)."""
+    q = Q.qvalues(stacks, world.w64, A) if qfn is None else qfn(stacks, A)
+    return q.max(axis=1)
 
 
 def children(world: World, pos, stack, A: int):
     return [E.step(pos, stack, a, world.delta, world.vel) for a in range(A)]
 
 
-def dfs(world: World, pos, stack, k: int, d: int, A: int, gamma: float) -> float:
+def dfs(world: World, pos, stack, k: int, d: int, A: int, gamma: float, qfn=None) -> float:
     """Value of a node at level k < d: max_a [ r_a + gamma * value(child_a) ],
     where a node at level d is worth max_a Q(s, a)."""
     kids = children(world, pos, stack, A)
     if k + 1 == d:
-        v = qmax(world, np.stack([s for _, s, _ in kids]), A)
+        v = qmax(world, np.stack([s for _, s, _ in kids]), A, qfn)
         return max(r + gamma * float(v[a]) for a, (_, _, r) in enumerate(kids))
-    return max(r + gamma * dfs(world, p, s, k + 1, d, A, gamma) for p, s, r in kids)
+    return max(r + gamma * dfs(world, p, s, k + 1, d, A, gamma, qfn) for p, s, r in kids)
 
 
-def root_values(world: World, pos, stack, d: int, A: int, gamma: float) -> np.ndarray:
+def root_values(world: World, pos, stack, d: int, A: int, gamma: float, qfn=None) -> np.ndarray:
     """Q_d(s_0, a) for every root action a (Eq. 1); d >= 1."""
     assert d >= 1
     out = np.empty(A)
     for a, (p, s, r) in enumerate(children(world, pos, stack, A)):
         if d == 1:
-            out[a] = r + gamma * float(qmax(world, s[None], A)[0])
+            out[a] = r + gamma * float(qmax(world, s[None], A, qfn)[0])
         else:
-            out[a] = r + gamma * dfs(world, p, s, 1, d, A, gamma)
+            out[a] = r + gamma * dfs(world, p, s, 1, d, A, gamma, qfn)
     return out
 
 
@@ -106,20 +108,24 @@ class Result:
 
 
 def search(world: World, pos, stack, d: int, A: int, gamma: float,
-           correction: bool = True, c: float = 1.0, mode: str = "eq6") -> Result:
+           correction: bool = True, c: float = 1.0, mode: str = "eq6",
+           leaf_qfn=None, corr_qfn=None) -> Result:
     """One root: the returned vector and action of the corrected search.
     mode "eq6" uses B of Eq. 6; mode "gev" uses the exact bias gap of
-    Lemma 3.2 with sigma = |delta| / sqrt(2)."""
-    q0 = Q.qvalues(stack, world.w64, A)
+    Lemma 3.2 with sigma = |delta| / sqrt(2).  `leaf_qfn` evaluates the
+    leaves (and the root at depth 0), `corr_qfn` the root and depth-1 nodes
+    the correction reads; both default to the FP64 network."""
     if d == 0:
+        q0 = Q.qvalues(stack, world.w64, A) if leaf_qfn is None else leaf_qfn(stack[None], A)[0]
         return Result(action=argmax_low(q0), q=q0.copy(), q0=q0, ties=tie_set(q0))
-    qd = root_values(world, pos, stack, d, A, gamma)
+    qd = root_values(world, pos, stack, d, A, gamma, leaf_qfn)
     if not correction:
         return Result(action=argmax_low(qd), q=qd.copy(), q_d=qd, ties=tie_set(qd))
+    q0 = Q.qvalues(stack, world.w64, A) if corr_qfn is None else corr_qfn(stack[None], A)[0]
     pi_o = argmax_low(q0)
     delta = np.empty(A)
     for a, (p, s, r) in enumerate(children(world, pos, stack, A)):
-        delta[a] = r + gamma * float(qmax(world, s[None], A)[0]) - q0[a]
+        delta[a] = r + gamma * float(qmax(world, s[None], A, corr_qfn)[0]) - q0[a]
     do = abs(delta[pi_o])
     de = float(np.mean([abs(delta[a]) for a in range(A) if a != pi_o]))
     if mode == "eq6":
@@ -133,6 +139,21 @@ def search(world: World, pos, stack, d: int, A: int, gamma: float,
             q[a] = qd[a] - c * gamma ** d * B
     return Result(action=argmax_low(q), q=q, q_d=qd, q0=q0, pi_o=pi_o, delta=delta, B=B,
                   ties=tie_set(q))
+
+
+def search_lowp(world: World, pos, stack, d: int, A: int, gamma: float, prec: str, ascale=None,
+                correction: bool = True, c: float = 1.0, mode: str = "eq6",
+                corr_prec: str = "fp64") -> Result:
+    """The search of `search` with every leaf (and the root at depth 0)
+    scored by the emulation of a low-precision network (``qnet.qvalues_lowp``:
+    each layer's operands rounded to `prec`, the sums in FP64).  The root and
+    depth-1 evaluations the correction reads use `corr_prec`: "fp64" (the
+    exact network; a matrix-core path that keeps them in FP32 is compared
+    against this) or the leaves' `prec`."""
+    def lowp(stacks, A_):
+        return Q.qvalues_lowp(stacks, world.w64, A_, prec, ascale=ascale)
+    return search(world, pos, stack, d, A, gamma, correction, c, mode, leaf_qfn=lowp,
+                  corr_qfn=None if corr_prec == "fp64" else lowp)
 
 
 def enumerate_nodes(world: World, pos, stack, d: int, A: int):

@@ -41,8 +41,9 @@ EXPORTS = (
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
     "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
+    "bcts_debug_qnet_siblings",
 )
-TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK = 0, 1, 2, 3
+TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32 = 0, 1, 2, 3, 4
 
 
 class EnvParamsC(ctypes.Structure):
@@ -90,6 +91,7 @@ _serve_config = _sig("bcts_serve_config", c_int32, _P, c_int32, c_int32)
 _request_bytes = _sig("bcts_request_bytes", c_size_t, c_int32, c_int32)
 _debug_expand = _sig("bcts_debug_expand", c_int32, _P, _P, _P, c_int32, c_int32, _P, _P, _P)
 _debug_qnet = _sig("bcts_debug_qnet", c_int32, _P, c_int32, _P, c_int32, _P)
+_debug_qnet_siblings = _sig("bcts_debug_qnet_siblings", c_int32, _P, c_int32, _P, c_int32, c_int32, _P)
 _set_timing = _sig("bcts_set_timing", c_int32, _P, c_int32)
 _get_timing = _sig("bcts_get_timing", c_int32, _P, _P)
 _set_tuning = _sig("bcts_set_tuning", c_int32, _P, c_int32, ctypes.c_int64)
@@ -314,6 +316,13 @@ def bcts_debug_qnet(ctx, stacks, A: int) -> np.ndarray:
     s = _arr(stacks, np.uint8)
     q = np.zeros((s.shape[0], A), np.float32)
     _check(ctx, _debug_qnet(ctx, s.shape[0], _ptr(s), A, _ptr(q)))
+    return q
+
+
+def bcts_debug_qnet_siblings(ctx, stacks, A: int, group: int) -> np.ndarray:
+    s = _arr(stacks, np.uint8)
+    q = np.zeros((s.shape[0], A), np.float32)
+    _check(ctx, _debug_qnet_siblings(ctx, s.shape[0], _ptr(s), A, group, _ptr(q)))
     return q
 
 

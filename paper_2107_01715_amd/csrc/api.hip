@@ -98,6 +98,14 @@ struct Plan {
   std::vector<FusedGroup> groups;      // sibling groups in item order
   struct Chunk { int g0, g1; long long i0, i1; };
   std::vector<Chunk> chunks;           // whole groups, ~chunk_items items each
+  // The correction's own Q-network inputs (the root and depth-1 evaluations
+  // of corrected roots) can run in FP32 whatever the leaf precision: they
+  // then occupy the item range [tail_item0, n_items), evaluated by the FP32
+  // layer kernels in the ranges of tail_chunks.  tail_item0 == n_items when
+  // every item runs at the search precision.
+  long long tail_item0 = 0;
+  std::vector<std::pair<long long, long long>> tail_chunks;
+  long long tail_chunk = 0;            // max items of a tail chunk
   size_t o_groups = 0;
   // arena offsets
   size_t o_root_pos = 0, o_root_stack = 0, o_roots = 0, o_segs = 0, o_V = 0, o_q0 = 0,
@@ -121,6 +129,7 @@ struct bcts_ctx {
   long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
   bool fused = true;
+  bool corr_fp32 = true;                // root / depth-1 evals of corrected roots in FP32
   int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
   // weights
   void* wmem = nullptr;
@@ -142,12 +151,23 @@ struct bcts_ctx {
   hipEvent_t tpin_ev[2] = {nullptr, nullptr};
   bool tpin_busy[2] = {false, false};
   int tpin_next = 0;
+  // cross-stream order of the arena: the stream of the last search enqueued
+  // on it and an event recorded after that search's work (see order_arena)
+  hipEvent_t arena_ev = nullptr;
+  hipStream_t arena_stream = nullptr;
+  bool arena_pending = false;
+  // the no-allocation entry point: the device's static scratch and a host
+  // staging buffer for its tables, reused once its last copy has finished
+  char* scratch = nullptr;
+  std::vector<char> na_tables;
+  hipEvent_t na_ev = nullptr;
+  bool na_pending = false;
   // timing: events of the last timed search (see collect_timing)
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> tev;      // [start, level 1..maxd, chunk x 6, qnet end, end]
   int t_maxd = 0, t_chunks = 0;
-  bool t_fused = false;
+  bool t_fused = false, t_tail = false;
   long long t_items = 0, t_nodes = 0;
   double t_ms[24] = {0};
   // serving
@@ -199,8 +219,34 @@ bcts_status ensure_pinned(bcts_ctx* c, size_t bytes) {
   return BCTS_OK;
 }
 
+// Work on the arena is ordered on the stream it is enqueued on.  A call on a
+// different stream than the previous search first waits (on the device) for
+// the event recorded after that search, so it cannot overwrite tables,
+// levels or activations the previous search still reads; the arena is only
+// freed once that event has completed.
+bcts_status order_arena(bcts_ctx* c, hipStream_t s) {
+  if (c->arena_pending && c->arena_stream != s) HIPCHECK(c, hipStreamWaitEvent(s, c->arena_ev, 0));
+  return BCTS_OK;
+}
+bcts_status arena_enqueued(bcts_ctx* c, hipStream_t s) {
+  if (!c->arena_ev) HIPCHECK(c, hipEventCreateWithFlags(&c->arena_ev, hipEventDisableTiming));
+  HIPCHECK(c, hipEventRecord(c->arena_ev, s));
+  c->arena_stream = s;
+  c->arena_pending = true;
+  return BCTS_OK;
+}
+bcts_status arena_idle(bcts_ctx* c) {
+  if (c->arena_pending) HIPCHECK(c, hipEventSynchronize(c->arena_ev));
+  c->arena_pending = false;
+  return BCTS_OK;
+}
+
 bcts_status ensure_arena(bcts_ctx* c, size_t bytes) {
   if (c->arena_bytes >= bytes) return BCTS_OK;
+  {
+    const bcts_status st = arena_idle(c);
+    if (st != BCTS_OK) return st;
+  }
   if (bytes + c->wbytes > c->budget)
     return fail(c, BCTS_E_NOMEM, "search needs %zu bytes of device memory; budget is %zu", bytes + c->wbytes,
                 c->budget);
@@ -250,10 +296,14 @@ bcts_status validate_pos(bcts_ctx* c, int n, const int32_t* pos) {
 // Build the plan: node counts, eval segments and the arena layout.
 // `q_stride` is the row stride of out_q; `qnet_only` makes every root a
 // single root-kind eval (debug Q-network on stacks).
+// `corr_fp32` moves the root and depth-1 evaluations of corrected roots to
+// the FP32 tail (chunks of `tail_chunk_items`) when `prec` is not FP32.
 void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
                const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
-               bool host_io, bool fused = false, int beam = 0) {
+               bool host_io, bool fused = false, int beam = 0, bool corr_fp32 = false,
+               long long tail_chunk_items = 8192) {
   p = Plan();
+  corr_fp32 = corr_fp32 && prec != P_FP32;
   p.beam = beam;
   p.fused = fused && prec != P_FP32;
   p.n = n;
@@ -303,8 +353,22 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
       ri.pen_o = (float)po;
     }
   }
-  // eval segments: per root, leaves, depth-1 nodes, root
+  // eval segments: per root, leaves, depth-1 nodes, root (with corr_fp32 the
+  // depth-1 and root segments of corrected roots follow all the others)
   long long item = 0;
+  auto add_corr_segs = [&](int r) {
+    RootInfo& ri = p.roots[r];
+    if (ri.corr && ri.d >= 2) {
+      p.segs.push_back(Seg{item, r, 1, ri.A, 1});
+      ri.d1_item = item;
+      item += ri.A;
+    }
+    if (ri.corr) {
+      p.segs.push_back(Seg{item, r, 0, ri.A, 2});
+      ri.root_item = item;
+      item += 1;
+    }
+  };
   for (int r = 0; r < n; ++r) {
     RootInfo& ri = p.roots[r];
     ri.leaf_item = ri.d1_item = ri.root_item = -1;
@@ -314,21 +378,32 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
       ri.leaf_item = item;
       item += cnt;
     }
-    if (ri.corr && ri.d >= 2) {
-      p.segs.push_back(Seg{item, r, 1, ri.A, 1});
-      ri.d1_item = item;
-      item += ri.A;
-    }
-    if (ri.d == 0 || ri.corr) {
+    if (ri.d == 0) {                   // no search: the root eval is the result
       p.segs.push_back(Seg{item, r, 0, ri.A, 2});
       ri.root_item = item;
       item += 1;
+    } else if (!corr_fp32) {
+      add_corr_segs(r);
     }
   }
+  const size_t main_segs = p.segs.size();
+  p.tail_item0 = item;
+  if (corr_fp32)
+    for (int r = 0; r < n; ++r)
+      if (p.roots[r].d >= 1) add_corr_segs(r);
   p.n_items = item;
+  {
+    const long long tc = std::max(1LL, tail_chunk_items);
+    for (long long i = p.tail_item0; i < p.n_items; i += tc) {
+      const long long e = std::min(p.n_items, i + tc);
+      p.tail_chunks.emplace_back(i, e);
+      p.tail_chunk = std::max(p.tail_chunk, e - i);
+    }
+  }
   // sibling groups: the A children of each level-(d-1) node, the A depth-1
   // nodes of a root, a root alone; chunks hold whole groups
-  for (const Seg& sg : p.segs) {
+  for (size_t si = 0; si < main_segs; ++si) {
+    const Seg& sg = p.segs[si];
     const RootInfo& ri = p.roots[sg.root];
     const long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : ri.lcnt[ri.d]);
     const int gsz = sg.kind == 2 ? 1 : ri.A;
@@ -380,8 +455,13 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
   }
   p.o_V = take(sizeof(float) * p.n_items);
   p.o_q0 = take(sizeof(float) * (size_t)n * kMaxA);
-  p.o_desc = take(sizeof(ItemDesc) * p.chunk);
-  p.o_ws = take(p.fused ? fused_workspace_bytes(p.chunk, prec) : qnet_workspace_bytes(p.chunk, prec));
+  p.o_desc = take(sizeof(ItemDesc) * std::max(p.chunk, p.tail_chunk));
+  {
+    size_t ws = p.chunks.empty() ? 0
+                : (p.fused ? fused_workspace_bytes(p.chunk, prec) : qnet_workspace_bytes(p.chunk, prec));
+    if (p.tail_chunk > 0) ws = std::max(ws, qnet_workspace_bytes(p.tail_chunk, P_FP32));
+    p.o_ws = take(ws);
+  }
   p.total = o;
 }
 
@@ -390,7 +470,7 @@ void plan_search(bcts_ctx* c, Plan& p, int n, const int32_t* depth, const int32_
                  const bcts_correction& corr, int q_stride, bool host_io) {
   const bool fz = c->fused && c->prec != P_FP32;
   make_plan(p, n, depth, A, gamma, corr, q_stride, fz ? c->fused_chunk_items : c->chunk_items, c->prec, host_io, fz,
-            c->beam);
+            c->beam, c->corr_fp32, c->chunk_items);
 }
 
 // Copy the plan's tables to `arena` through the pinned staging buffer `h`
@@ -412,6 +492,10 @@ bcts_status upload_tables_at(bcts_ctx* c, const Plan& p, char* arena, char* h, h
 // stages a search while the previous one still runs.  The device copy is
 // ordered on `s` after the previous search's kernels, which read the tables.
 bcts_status upload_tables(bcts_ctx* c, const Plan& p, hipStream_t s) {
+  {
+    const bcts_status st = order_arena(c, s);
+    if (st != BCTS_OK) return st;
+  }
   const int b = c->tpin_next;
   if (c->tpin_busy[b]) {
     HIPCHECK(c, hipEventSynchronize(c->tpin_ev[b]));
@@ -492,6 +576,15 @@ bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameB
     launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr);
     if (cev) HIPCHECK(c, hipEventRecord(cev[5], s));
   }
+  // the correction's root and depth-1 evaluations in FP32 (layer kernels)
+  if (ev && !p.tail_chunks.empty()) HIPCHECK(c, hipEventRecord(ev[6 * nchunks], s));
+  for (const auto& tc : p.tail_chunks) {
+    const long long cnt = tc.second - tc.first;
+    launch_item_desc(tc.first, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc,
+                     s);
+    launch_qnet(P_FP32, c->q, desc, cnt, A + p.o_ws, V + tc.first, q0, s, nullptr);
+  }
+  if (ev && !p.tail_chunks.empty()) HIPCHECK(c, hipEventRecord(ev[6 * nchunks + 1], s));
   return BCTS_OK;
 }
 
@@ -502,13 +595,14 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
   const int nchunks = (int)p.chunks.size();
   hipEvent_t* ev = nullptr;
   if (timed) {
-    bcts_status st = ensure_events(c, (size_t)(3 + p.maxd + 6 * nchunks));
+    bcts_status st = ensure_events(c, (size_t)(5 + p.maxd + 6 * nchunks));
     if (st != BCTS_OK) return st;
     ev = c->tev.data();
     c->t_maxd = p.maxd;
     c->t_chunks = nchunks;
     c->t_fused = p.fused;
     c->t_items = p.n_items;
+    c->t_tail = !p.tail_chunks.empty();
     c->t_nodes = 0;
     for (int k = 1; k <= p.maxd; ++k) c->t_nodes += p.lvl_count[k];
     HIPCHECK(c, hipEventRecord(ev[0], s));
@@ -542,11 +636,11 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
     bcts_status st = enqueue_qnet_stage(c, p, A, fb, s, timed ? ev + 1 + p.maxd : nullptr);
     if (st != BCTS_OK) return st;
   }
-  if (timed) HIPCHECK(c, hipEventRecord(ev[1 + p.maxd + 6 * nchunks], s));
+  if (timed) HIPCHECK(c, hipEventRecord(ev[3 + p.maxd + 6 * nchunks], s));
   LevelRet lr{};
   for (int k = 1; k <= p.maxd; ++k) lr.ret[k] = reinterpret_cast<const float*>(A + p.o_ret[k]);
   launch_backup_correct(p.n, roots, V, q0, lr, gamma, corr_scale, d_act, d_q, s);
-  if (timed) HIPCHECK(c, hipEventRecord(ev[2 + p.maxd + 6 * nchunks], s));
+  if (timed) HIPCHECK(c, hipEventRecord(ev[4 + p.maxd + 6 * nchunks], s));
   HIPCHECK(c, hipGetLastError());
   return BCTS_OK;
 }
@@ -560,11 +654,14 @@ bcts_status enqueue_search(bcts_ctx* c, const Plan& p, const int32_t* d_pos, con
 // Per-stage and per-kernel durations of the last timed search:
 // [0] expansion, [1] Q-network, [2] backup + correction, [3] total (ms);
 // [4..8] conv1, conv2, conv3, fc1, fc2 summed over chunks (ms); [9] chunks;
-// [10..15] expansion of levels 1..6 (ms); [16] eval items; [17] new nodes.
+// [10..15] expansion of levels 1..6 (ms); [16] eval items; [17] new nodes;
+// [18] fused kernel ran; [19] FP32 correction evaluations (ms).
+// Events: [0] start, [k] after level k, then 6 per chunk, 2 around the FP32
+// correction evaluations, the Q-network end and the search end.
 bcts_status collect_timing(bcts_ctx* c) {
   const int D = c->t_maxd, C = c->t_chunks;
   hipEvent_t* ev = c->tev.data();
-  const int q_end = 1 + D + 6 * C, end = q_end + 1;
+  const int tail0 = 1 + D + 6 * C, q_end = tail0 + 2, end = q_end + 1;
   HIPCHECK(c, hipEventSynchronize(ev[end]));
   auto el = [&](int a, int b) -> double {
     float ms = 0.f;
@@ -583,6 +680,7 @@ bcts_status collect_timing(bcts_ctx* c) {
   c->t_ms[16] = (double)c->t_items;
   c->t_ms[17] = (double)c->t_nodes;
   c->t_ms[18] = c->t_fused ? 1.0 : 0.0;
+  c->t_ms[19] = c->t_tail ? el(tail0, tail0 + 1) : 0.0;
   return BCTS_OK;
 }
 
@@ -617,6 +715,7 @@ bcts_status search_host(bcts_ctx* c, int n, const int32_t* pos, const uint8_t* s
   HIPCHECK(c, hipMemcpyAsync(out_action, d_act, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   HIPCHECK(c, hipMemcpyAsync(out_q, d_q, sizeof(float) * (size_t)n * q_stride, hipMemcpyDeviceToHost, s));
   HIPCHECK(c, hipStreamSynchronize(s));
+  c->arena_pending = false;
   if (c->timing) return collect_timing(c);
   return BCTS_OK;
 }
@@ -694,8 +793,9 @@ struct ServeEngine {
   long long chunk_items() const { return (c->fused && c->prec != P_FP32) ? 8 * chunk : chunk; }
   size_t fixed_bytes() const {
     const long long ch = chunk_items() + kMaxA;
-    const size_t ws = (c->fused && c->prec != P_FP32) ? fused_workspace_bytes(ch, c->prec)
-                                                       : qnet_workspace_bytes(ch, c->prec);
+    size_t ws = (c->fused && c->prec != P_FP32) ? fused_workspace_bytes(ch, c->prec)
+                                                 : qnet_workspace_bytes(ch, c->prec);
+    if (c->corr_fp32 && c->prec != P_FP32) ws = std::max(ws, qnet_workspace_bytes(chunk, P_FP32));
     return ws + sizeof(ItemDesc) * ch + 8 * kAlign;
   }
 
@@ -772,10 +872,12 @@ struct ServeEngine {
     for (int i = 0; i < n; ++i) { dep[i] = queue[i].d; Av[i] = queue[i].A; }
     Plan p;
     const bool fz = c->fused && c->prec != P_FP32;
-    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam);
+    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam,
+              c->corr_fp32, chunk);
     while (p.total > slot_cap && n > 1) {   // alignment slack: shrink the batch
       --n;
-      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam);
+      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam,
+                c->corr_fp32, chunk);
     }
     if (p.total > slot_cap) return fail(c, BCTS_E_NOMEM, "request does not fit a serving slot");
     if (sl.arena_bytes < slot_cap) {
@@ -893,6 +995,8 @@ void bcts_destroy(bcts_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->arena_pending) (void)hipEventSynchronize(c->arena_ev);
+  if (c->na_pending) (void)hipEventSynchronize(c->na_ev);
   delete c->serve;
   if (c->arena) (void)hipFree(c->arena);
   if (c->wmem) (void)hipFree(c->wmem);
@@ -905,6 +1009,8 @@ void bcts_destroy(bcts_ctx* c) {
   }
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->arena_ev) (void)hipEventDestroy(c->arena_ev);
+  if (c->na_ev) (void)hipEventDestroy(c->na_ev);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -916,6 +1022,10 @@ bcts_status bcts_reset(bcts_ctx* c) {
   if (!c) return BCTS_E_INVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->arena_pending) (void)hipEventSynchronize(c->arena_ev);
+  c->arena_pending = false;
+  if (c->na_pending) (void)hipEventSynchronize(c->na_ev);
+  c->na_pending = false;
   (void)hipGetLastError();
   if (c->serve) c->serve->drop_all();
   if (c->arena) (void)hipFree(c->arena);
@@ -1161,6 +1271,7 @@ bcts_status bcts_search_batch_device(bcts_ctx* c, int32_t n, const int32_t* d_po
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
   st = enqueue_search(c, p, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, s, c->timing);
   if (st != BCTS_OK) return st;
+  if ((st = arena_enqueued(c, s)) != BCTS_OK) return st;
   if (c->timing) return collect_timing(c);
   return BCTS_OK;
 }
@@ -1182,6 +1293,7 @@ bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
   HIPCHECK(c, hipStreamSynchronize(s));
+  c->arena_pending = false;
   hipStream_t cap;
   HIPCHECK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
@@ -1261,17 +1373,53 @@ bcts_status bcts_debug_expand(bcts_ctx* c, const int32_t* pos, const uint8_t* st
   return BCTS_OK;
 }
 
-bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32_t A, float* out_q) {
+}  // extern "C"
+
+namespace {
+// Q-network on n host stacks; with group > 1 consecutive stacks form sibling
+// groups of that size (the last one may be shorter) for the fused kernel,
+// which then computes their shared channels 0..2 once per group.
+bcts_status debug_qnet_impl(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32_t A, int32_t group,
+                            float* out_q) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
   if (n <= 0 || !stacks || !out_q) return fail(c, BCTS_E_INVAL, "bad arguments");
   if (A < 1 || A > kMaxA) return fail(c, BCTS_E_INVAL, "A=%d outside [1,18]", A);
+  if (group < 1 || group > kMaxA) return fail(c, BCTS_E_INVAL, "group=%d outside [1,18]", group);
+  for (long long i = 0; i < n; ++i) {
+    const long long first = i / group * group;
+    if (i != first &&
+        std::memcmp(stacks + (size_t)i * 4 * kFrameBytes, stacks + (size_t)first * 4 * kFrameBytes,
+                    (size_t)3 * kFrameBytes) != 0)
+      return fail(c, BCTS_E_INVAL, "stack %lld does not share channels 0..2 with its group's first stack", i);
+  }
   if (!c->qnet_set) return fail(c, BCTS_E_STATE, "no Q-network set");
   HIPCHECK(c, hipSetDevice(c->device));
   std::vector<int32_t> dep(n, 0), Av(n, A);
   bcts_correction off{0, 0.f, 0};
   Plan p;
   plan_search(c, p, n, dep.data(), Av.data(), 1.f, off, kMaxA, true);
+  if (group > 1 && p.fused) {
+    // regroup the one-item root groups into sibling groups, chunks of whole groups
+    p.groups.clear();
+    for (long long i = 0; i < n; i += group) p.groups.push_back(FusedGroup{i, (int)std::min<long long>(group, n - i), 0});
+    const long long target = std::max(1LL, c->fused_chunk_items);
+    p.chunks.clear();
+    int g = 0;
+    while (g < (int)p.groups.size()) {
+      Plan::Chunk ch;
+      ch.g0 = g;
+      ch.i0 = p.groups[g].item0;
+      long long items = 0;
+      while (g < (int)p.groups.size() && (items == 0 || items + p.groups[g].count <= target)) {
+        items += p.groups[g].count;
+        ++g;
+      }
+      ch.g1 = g;
+      ch.i1 = ch.i0 + items;
+      p.chunks.push_back(ch);
+    }
+  }
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   hipStream_t s = c->stream;
   if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
@@ -1288,6 +1436,18 @@ bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < A; ++a) out_q[(size_t)i * A + a] = h[(size_t)i * kMaxA + a];
   return BCTS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bcts_status bcts_debug_qnet(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32_t A, float* out_q) {
+  return debug_qnet_impl(c, n, stacks, A, 1, out_q);
+}
+
+bcts_status bcts_debug_qnet_siblings(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32_t A, int32_t group,
+                                     float* out_q) {
+  return debug_qnet_impl(c, n, stacks, A, group, out_q);
 }
 
 size_t bcts_request_bytes(int32_t depth, int32_t A) {
@@ -1388,6 +1548,9 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
       if (value < 1 || value > (1LL << 22)) return fail(c, BCTS_E_INVAL, "layer chunk out of range");
       c->chunk_items = value;
       return BCTS_OK;
+    case BCTS_TUNE_CORR_FP32:
+      c->corr_fp32 = value != 0;
+      return BCTS_OK;
     default:
       return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
@@ -1400,6 +1563,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_FUSED_ROUND: *value = c->fused_T; return BCTS_OK;
     case BCTS_TUNE_FUSED_CHUNK: *value = c->fused_chunk_items; return BCTS_OK;
     case BCTS_TUNE_LAYER_CHUNK: *value = c->chunk_items; return BCTS_OK;
+    case BCTS_TUNE_CORR_FP32: *value = c->corr_fp32 ? 1 : 0; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }
@@ -1647,9 +1811,10 @@ bcts_status bcts_mlp_search_device(bcts_ctx* c, int32_t n_roots, const float* d_
   if ((st = mlp_plan(c, n_roots, depth, false, p)) != BCTS_OK) return st;
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+  if ((st = order_arena(c, s)) != BCTS_OK) return st;
   mlp_enqueue(c, p, n_roots, depth, d_states, gamma, corr, d_out_action, d_out_q, s);
   HIPCHECK(c, hipGetLastError());
-  return BCTS_OK;
+  return arena_enqueued(c, s);
 }
 
 bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, int32_t depth, float gamma,
@@ -1664,6 +1829,7 @@ bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, i
   MlpPlan p;
   if ((st = mlp_plan(c, n_roots, depth, true, p)) != BCTS_OK) return st;
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  if ((st = order_arena(c, c->stream)) != BCTS_OK) return st;
   const int A = c->mlp.A;
   HIPCHECK(c, hipMemcpyAsync(c->arena + p.in_states, states, sizeof(float) * 100 * (size_t)n_roots,
                              hipMemcpyHostToDevice, c->stream));
@@ -1675,6 +1841,7 @@ bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, i
   HIPCHECK(c, hipMemcpyAsync(out_action, d_act, sizeof(int32_t) * (size_t)n_roots, hipMemcpyDeviceToHost, c->stream));
   HIPCHECK(c, hipMemcpyAsync(out_q, d_q, sizeof(float) * (size_t)n_roots * A, hipMemcpyDeviceToHost, c->stream));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->arena_pending = false;
   return BCTS_OK;
 }
 

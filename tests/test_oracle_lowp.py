@@ -21,6 +21,24 @@ def test_round_e4m3_known_values():
     np.testing.assert_array_equal(Q.round_e4m3(x), want)
 
 
+@pytest.mark.parametrize("scale", [1e-4, 0.05, 1.0, 300.0])
+def test_roundings_match_torch_conversions(scale):
+    """The bit-level roundings against torch's own float32 -> bfloat16 and
+    float32 -> float8_e4m3fn conversions (a library routine), on random
+    values across the normal and subnormal ranges, exact halves included."""
+    import torch
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal(200000) * scale).astype(np.float32)
+    halves = np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 17.0, 19.0, 2 ** -8 + 2 ** -10, 3 * 2 ** -10],
+                      dtype=np.float32)
+    x = np.concatenate([x, halves, -halves])
+    want_bf = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(Q.round_bf16(x), want_bf)
+    y = np.clip(x, -448.0, 448.0)
+    want_f8 = torch.from_numpy(y).to(torch.float8_e4m3fn).double().numpy()
+    np.testing.assert_array_equal(Q.round_e4m3(x), want_f8)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_lowp_reduces_to_fp64_without_rounding(monkeypatch, prec):
     w64 = Q.prepare(W.qnet_weights(7))
@@ -39,3 +57,70 @@ def test_lowp_error_is_small_but_present(prec, bound):
     got = Q.qvalues_lowp(st, w64, 18, prec, ascale=[1.0, 100.0, 100.0, 100.0, 100.0])
     rel = np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)
     assert 0 < rel.max() < bound
+
+
+# ---- the low-precision search (leaves through the emulation) ---------------
+import itertools  # noqa: E402
+
+from oracle import env as E, search as S  # noqa: E402
+
+ASCALE = [1.0, 37.0, 5.0, 123.0, 9.0]
+
+
+def brute_force_lowp_qd(world, pos, stack, d, A, gamma, prec):
+    """Every action sequence rolled out from the root by hand; the leaf adds
+    gamma^d max of the emulated network; best sequence per first action."""
+    best = np.full(A, -np.inf)
+    for seq in itertools.product(range(A), repeat=d):
+        p, s, ret = np.asarray(pos, dtype=np.int64), stack, 0.0
+        for t, a in enumerate(seq):
+            p, s, r = E.step(p, s, a, world.delta, world.vel)
+            ret += gamma ** t * r
+        v = Q.qvalues_lowp(s, world.w64, A, prec, ascale=ASCALE).max()
+        best[seq[0]] = max(best[seq[0]], ret + gamma ** d * float(v))
+    return best
+
+
+@pytest.mark.parametrize("prec,d,A", [("bf16", 1, 4), ("bf16", 2, 4), ("fp8", 2, 3)])
+def test_search_lowp_equals_brute_force(world_c1, prec, d, A):
+    pos, st = W.roots(1001, 2)
+    for r in range(2):
+        got = S.search_lowp(world_c1, pos[r], st[r], d, A, 0.99, prec, ascale=ASCALE, correction=False)
+        want = brute_force_lowp_qd(world_c1, pos[r], st[r], d, A, 0.99, prec)
+        np.testing.assert_allclose(got.q, want, rtol=1e-12, atol=1e-12)
+
+
+def test_search_lowp_keeps_fp64_correction_inputs(world_c1):
+    """With corr_prec="fp64" pi_o, the Bellman errors and B are the FP64
+    search's; only the backed-up values carry the leaves' rounding."""
+    pos, st = W.roots(1001, 3)
+    for r in range(3):
+        lo = S.search_lowp(world_c1, pos[r], st[r], 2, 4, 0.99, "bf16")
+        hi = S.search(world_c1, pos[r], st[r], 2, 4, 0.99)
+        assert lo.pi_o == hi.pi_o
+        np.testing.assert_array_equal(lo.delta, hi.delta)
+        assert lo.B == hi.B
+        assert not np.array_equal(lo.q_d, hi.q_d)
+
+
+def test_search_lowp_rounds_correction_inputs_on_request(world_c1):
+    """corr_prec="bf16" sends the root and depth-1 evaluations through the
+    emulation too: the root values the correction reads are the emulated
+    network's, not the FP64 one's."""
+    pos, st = W.roots(1001, 1)
+    lo = S.search_lowp(world_c1, pos[0], st[0], 2, 4, 0.99, "bf16", corr_prec="bf16")
+    want_q0 = Q.qvalues_lowp(st[0], world_c1.w64, 4, "bf16")
+    np.testing.assert_array_equal(lo.q0, want_q0)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_search_lowp_reduces_to_fp64_without_rounding(world_c1, monkeypatch, prec):
+    monkeypatch.setattr(Q, "round_bf16", lambda x: np.asarray(x, dtype=np.float64))
+    monkeypatch.setattr(Q, "round_e4m3", lambda x: np.asarray(x, dtype=np.float64))
+    pos, st = W.roots(1002, 2)
+    for d in (0, 1, 2):
+        for r in range(2):
+            lo = S.search_lowp(world_c1, pos[r], st[r], d, 4, 0.99, prec, ascale=ASCALE, corr_prec=prec)
+            hi = S.search(world_c1, pos[r], st[r], d, 4, 0.99)
+            np.testing.assert_allclose(lo.q, hi.q, rtol=1e-11, atol=1e-12)
+            assert lo.action == hi.action
