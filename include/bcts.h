@@ -188,8 +188,11 @@ bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_
  *                          -- are evaluated in FP32 whatever the precision,
  *                          so that a low-precision rounding cannot flip pi_o
  *                          or move delta; the leaves (and depth-0 searches)
- *                          keep the search precision.  0 = every evaluation
- *                          at the search precision.                         */
+ *                          keep the search precision.  At depth 1 the
+ *                          depth-1 nodes are the leaves; their A FP32
+ *                          evaluations are then extra work.  0 = every
+ *                          evaluation at the search precision (at depth 1
+ *                          the Bellman errors read the leaves' values). */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,

@@ -356,9 +356,11 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
   // eval segments: per root, leaves, depth-1 nodes, root (with corr_fp32 the
   // depth-1 and root segments of corrected roots follow all the others)
   long long item = 0;
+  // (at depth 1 the depth-1 nodes are the leaves: their values serve the
+  // Bellman errors unless those are taken in FP32, which needs A FP32 evals)
   auto add_corr_segs = [&](int r) {
     RootInfo& ri = p.roots[r];
-    if (ri.corr && ri.d >= 2) {
+    if (ri.corr && (ri.d >= 2 || corr_fp32)) {
       p.segs.push_back(Seg{item, r, 1, ri.A, 1});
       ri.d1_item = item;
       item += ri.A;

@@ -56,7 +56,7 @@ backup_kernel(int n_roots, const RootInfo* __restrict__ roots, const float* __re
     if (ri.corr) {
       const float* Q0 = q0 + (long long)r * kMaxA;
       const float* r1 = level_ret.ret[1] + ri.base[1];          // depth-1 returns = rewards
-      const float* v1 = V + (d >= 2 ? ri.d1_item : ri.leaf_item);
+      const float* v1 = V + (ri.d1_item >= 0 ? ri.d1_item : ri.leaf_item);
       int pi_o = 0;
       for (int a = 1; a < A; ++a)
         if (Q0[a] > Q0[pi_o]) pi_o = a;

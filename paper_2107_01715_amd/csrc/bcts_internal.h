@@ -58,7 +58,7 @@ struct RootInfo {
   long long kbase[kMaxD + 1];  // level k cut by the beam: first entry of this root's keep list, else -1
   long long leaf_blk;          // leaves per root action (A^(d-1) unless cut)
   long long leaf_item;         // first leaf eval item (d >= 1), else -1
-  long long d1_item;           // first depth-1 eval item (d >= 2 and corr), else -1
+  long long d1_item;           // first depth-1 eval item (corr and d >= 2, or d = 1 with FP32 correction evals), else -1
   long long root_item;         // root eval item, else -1
 };
 

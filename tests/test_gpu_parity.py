@@ -158,13 +158,15 @@ def test_device_and_graph_equal_host(lib, setup):
     ctx.set_precision(lib.FP32)
 
 
-@pytest.mark.parametrize("prec,tol,tol_med", [("BF16", 2e-3, 1e-4), ("FP8", 5e-2, 1e-3)])
+@pytest.mark.parametrize("prec,tol,tol_med", [("BF16", 2e-3, 1e-4), ("FP8", 2e-3, 1e-4)])
 def test_lowp_qnet_matches_emulation(lib, setup, prec, tol, tol_med):
     """BF16 / FP8 matrix-core Q-network vs the oracle's emulation of the same
-    operand roundings (FP64 sums, same per-layer scales).  An activation whose
-    FP32 value sits at a rounding boundary may round the other way than in
-    the FP64 emulation (one e4m3 step is 12.5%), so most stacks agree to FP32
-    rounding (the median bound) and a few differ by such a flip (the max)."""
+    operand roundings (same per-layer scales; BF16 products summed in FP64,
+    FP8 products summed as the FP8 matrix instructions sum them).  An
+    activation whose FP32 value sits at a rounding boundary may round the
+    other way than in the emulation, so most stacks agree to FP32 rounding
+    (the median bound) and a rare one differs by such a flip (the max: one
+    BF16 step is 2^-8 of the activation; the FP8 stacks here have none)."""
     ctx, world, _ = setup
     _, st = W.roots(21, 24)
     dense = np.random.default_rng(8).integers(0, 256, size=(4, 4, 84, 84), dtype=np.uint8)

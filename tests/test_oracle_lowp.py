@@ -45,8 +45,61 @@ def test_lowp_reduces_to_fp64_without_rounding(monkeypatch, prec):
     _, st = W.roots(4, 3)
     monkeypatch.setattr(Q, "round_bf16", lambda x: np.asarray(x, dtype=np.float64))
     monkeypatch.setattr(Q, "round_e4m3", lambda x: np.asarray(x, dtype=np.float64))
+    monkeypatch.setattr(Q, "fp8_dot", lambda X, Wm: X @ Wm.T)       # exact sums
     got = Q.qvalues_lowp(st, w64, 18, prec, ascale=[1.0, 37.0, 5.0, 123.0, 9.0])
     np.testing.assert_allclose(got, Q.qvalues(st, w64, 18), rtol=1e-11, atol=1e-13)
+
+
+def _dot1(a_vals, b_vals=None):
+    """One row x one column of the grouped FP8 sum; K padded to a multiple of 8."""
+    a = np.asarray(a_vals, dtype=np.float64)
+    b = np.ones_like(a) if b_vals is None else np.asarray(b_vals, dtype=np.float64)
+    k = -(-a.size // 8) * 8
+    A = np.zeros((1, k)); B = np.zeros((1, k))
+    A[0, :a.size], B[0, :b.size] = a, b
+    return float(Q.dot_fp8_groups(A, B)[0, 0])
+
+
+def test_fp8_group_sum_hand_worked():
+    """Hand-worked values of the FP8 matrix-core sum rule (groups of 8
+    consecutive K values; products truncated toward zero to multiples of
+    2^(E-13), E the group's largest sum of operand exponent fields; zero
+    products ignored; subnormals at exponent -6)."""
+    t = 2.0 ** -6
+    # 256 at k = 0: the 7 tiny products of its group fall below the grid
+    # 2^(8-13) = 2^-5; the other 3 groups of 8 keep theirs
+    assert _dot1([256.0] + [t] * 31) == 256.0 + 24 * t
+    # a tiny product in the next group is kept whole
+    assert _dot1([256.0] + [0.0] * 7 + [t]) == 256.0 + t
+    # truncation toward zero, for either sign: 1.5 * 2^-5 -> 2^-5
+    assert _dot1([256.0, 1.5 * 2 ** -5]) == 256.0 + 2 ** -5
+    assert _dot1([256.0, -1.5 * 2 ** -5]) == 256.0 - 2 ** -5
+    assert _dot1([-256.0, 1.5 * 2 ** -5]) == -256.0 + 2 ** -5
+    # E is the sum of the exponent fields, not the product's exponent:
+    # 1.75 * 1.75 = 3.0625 has fields 0 + 0, so 2^-13 stays; 1 * 2 has 0 + 1
+    assert _dot1([1.75, 2.0 ** -7], [1.75, 2.0 ** -6]) == 3.0625 + 2.0 ** -13
+    assert _dot1([1.0, 2.0 ** -7], [2.0, 2.0 ** -6]) == 2.0
+    # products with a zero operand take no part in E
+    assert _dot1([0.0, 2.0 ** -6], [448.0, 2.0 ** -6]) == 2.0 ** -12
+    # a subnormal operand counts as exponent -6: 2^-9 * 448 has E = 2
+    assert _dot1([2.0 ** -9, 2.0 ** -6], [448.0, 2.0 ** -6]) == 2.0 ** -9 * 448.0
+    assert _dot1([2.0 ** -9, 2.0 ** -6], [448.0, 2.0 ** -5]) == 2.0 ** -9 * 448.0 + 2.0 ** -11
+    # products within 2^7 of the group's largest are exact (8-bit products)
+    rng = np.random.default_rng(3)
+    a = Q.round_e4m3(rng.uniform(1.0, 2.0, 64))
+    b = Q.round_e4m3(rng.uniform(1.0, 2.0, 64))
+    assert _dot1(a, b) == float(np.dot(a, b))
+
+
+def test_fp8_conv_grouping_reduces_to_conv2d(monkeypatch):
+    """With exact sums the grouped convolution (its K reorderings) equals the
+    plain convolution, for the frame layer and the channels-last layers."""
+    monkeypatch.setattr(Q, "fp8_dot", lambda X, Wm: X @ Wm.T)
+    rng = np.random.default_rng(5)
+    for (C, H, O, k, s, inner) in ((4, 84, 32, 8, 4, False), (32, 20, 64, 4, 2, True), (64, 9, 64, 3, 1, True)):
+        x = rng.standard_normal((2, C, H, H))
+        w = rng.standard_normal((O, C, k, k))
+        np.testing.assert_allclose(Q.conv_fp8(x, w, s, inner), Q.conv2d(x, w, np.zeros(O), s), rtol=1e-12, atol=1e-12)
 
 
 @pytest.mark.parametrize("prec,bound", [("bf16", 0.02), ("fp8", 0.3)])
@@ -117,6 +170,7 @@ def test_search_lowp_rounds_correction_inputs_on_request(world_c1):
 def test_search_lowp_reduces_to_fp64_without_rounding(world_c1, monkeypatch, prec):
     monkeypatch.setattr(Q, "round_bf16", lambda x: np.asarray(x, dtype=np.float64))
     monkeypatch.setattr(Q, "round_e4m3", lambda x: np.asarray(x, dtype=np.float64))
+    monkeypatch.setattr(Q, "fp8_dot", lambda X, Wm: X @ Wm.T)       # exact sums
     pos, st = W.roots(1002, 2)
     for d in (0, 1, 2):
         for r in range(2):
