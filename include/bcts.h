@@ -163,6 +163,27 @@ bcts_status bcts_search_batch_device(bcts_ctx* ctx, int32_t n_roots, const int32
                                      const int32_t* A, float gamma, bcts_correction corr,
                                      int32_t* d_out_action, float* d_out_q, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the search
+ * of bcts_search_batch_device (same arguments, same kernels, same results
+ * bit for bit), with every device buffer the search needs beyond the
+ * caller's inputs and outputs -- plan tables, expanded levels, eval values,
+ * Q-network activations -- carved from a static device array of 128 MiB that
+ * the library holds on each device until the process ends.  No device or
+ * pinned memory is allocated or freed by this call (the plan is made in
+ * ordinary host memory; its tables are copied from there).  A search that
+ * needs more than the array, even with the Q-network chunks halved down to
+ * 256 stacks, returns BCTS_E_NOMEM and enqueues nothing (one root at A = 18,
+ * depth 3 fits; the 256-root headline batch does not).  The array keeps the
+ * last call's contents and every context on the device shares it: calls of
+ * one context are ordered (a call on another stream first waits for the
+ * previous one on the device), but calls from different contexts on one
+ * device that overlap in time race.  No timing is recorded.                */
+bcts_status bcts_search_batch_device_noalloc(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos,
+                                             const uint8_t* d_stacks, const int32_t* depth,
+                                             const int32_t* A, float gamma, bcts_correction corr,
+                                             int32_t* d_out_action, float* d_out_q, void* hip_stream);
+
 /* Capture the device search of one batch shape into a HIP graph and replay
  * it `replays` times (buffers as in bcts_search_batch_device, stream NULL =
  * context stream).  Results of every replay equal the eager search.        */

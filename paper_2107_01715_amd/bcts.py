@@ -41,7 +41,7 @@ EXPORTS = (
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
     "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
-    "bcts_debug_qnet_siblings",
+    "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32 = 0, 1, 2, 3, 4
 
@@ -82,6 +82,8 @@ _search = _sig("bcts_search", c_int32, _P, c_int32, _P, _P, c_int32, c_int32, c_
 _search_batch = _sig("bcts_search_batch", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, CorrectionC, _P, _P)
 _search_batch_device = _sig("bcts_search_batch_device", c_int32, _P, c_int32, _P, _P, _P, _P, c_float,
                             CorrectionC, _P, _P, _P)
+_search_batch_device_noalloc = _sig("bcts_search_batch_device_noalloc", c_int32, _P, c_int32, _P, _P, _P, _P,
+                                    c_float, CorrectionC, _P, _P, _P)
 _search_batch_graph = _sig("bcts_search_batch_graph", c_int32, _P, c_int32, _P, _P, _P, _P, c_float,
                            CorrectionC, _P, _P, c_int32, _P)
 _submit = _sig("bcts_submit", c_int32, _P, _P, _P, c_int32, c_int32, c_float, CorrectionC, POINTER(c_uint64))
@@ -220,6 +222,16 @@ def bcts_search_batch_device(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t,
     _check(ctx, _search_batch_device(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8),
                                      _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32, n),
                                      _dev(q_t, torch.float32, n * MAX_A), s))
+
+
+def bcts_search_batch_device_noalloc(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, stream=None):
+    n = pos_t.shape[0]
+    d = _arr(depth, np.int32)
+    a = _arr(A, np.int32)
+    s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(ctx, _search_batch_device_noalloc(ctx, n, _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8),
+                                             _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32, n),
+                                             _dev(q_t, torch.float32, n * MAX_A), s))
 
 
 def bcts_search_batch_graph(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, replays=1, stream=None):

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -156,12 +157,16 @@ struct bcts_ctx {
   hipEvent_t arena_ev = nullptr;
   hipStream_t arena_stream = nullptr;
   bool arena_pending = false;
-  // the no-allocation entry point: the device's static scratch and a host
-  // staging buffer for its tables, reused once its last copy has finished
+  // the no-allocation entry point: the device's static scratch (its device
+  // address, looked up at bcts_create) and a host staging buffer for its
+  // tables, reused once its last copy has finished (na_copy_ev); na_ev marks
+  // the end of the last search enqueued on the scratch, on stream na_stream
   char* scratch = nullptr;
+  std::string scratch_err;
   std::vector<char> na_tables;
-  hipEvent_t na_ev = nullptr;
-  bool na_pending = false;
+  hipEvent_t na_ev = nullptr, na_copy_ev = nullptr;
+  hipStream_t na_stream = nullptr;
+  bool na_pending = false, na_copy_pending = false;
   // timing: events of the last timed search (see collect_timing)
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -965,6 +970,44 @@ static bcts_status refuse_if_serving(bcts_ctx* c, const char* what) {
   return BCTS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of bcts_search_batch_device_noalloc: device memory the
+// library never allocates at run time.  Host code uses the array's name only
+// to look up its device address (once per device, at bcts_create); kernels
+// receive that address, as they receive the arena in the other entry points.
+// Each device holds its own copy until the process ends; every context on a
+// device shares it.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevs = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevs] = {};
+
+// The device address of `scratch` on the current device (c->device).
+void scratch_setup(bcts_ctx* c) {
+  if (c->device >= kScratchDevs) {
+    c->scratch_err = "device index beyond the static scratch table";
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[c->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      c->scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return;
+    }
+    g_scratch_ptr[c->device] = static_cast<char*>(ptr);
+  }
+  c->scratch = g_scratch_ptr[c->device];
+}
+
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -984,11 +1027,14 @@ bcts_status bcts_create(int hip_device, size_t hbm_budget_bytes, bcts_ctx** out)
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
   bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; i < 4 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->na_ev, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->na_copy_ev, hipEventDisableTiming) == hipSuccess;
   if (!ok) {                          // release what was created
     (void)hipGetLastError();
     bcts_destroy(c);
     return BCTS_E_HIP;
   }
+  scratch_setup(c);                   // device address of the static scratch (device current)
   *out = c;
   return BCTS_OK;
 }
@@ -999,6 +1045,7 @@ void bcts_destroy(bcts_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->arena_pending) (void)hipEventSynchronize(c->arena_ev);
   if (c->na_pending) (void)hipEventSynchronize(c->na_ev);
+  if (c->na_copy_pending) (void)hipEventSynchronize(c->na_copy_ev);
   delete c->serve;
   if (c->arena) (void)hipFree(c->arena);
   if (c->wmem) (void)hipFree(c->wmem);
@@ -1013,6 +1060,7 @@ void bcts_destroy(bcts_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->arena_ev) (void)hipEventDestroy(c->arena_ev);
   if (c->na_ev) (void)hipEventDestroy(c->na_ev);
+  if (c->na_copy_ev) (void)hipEventDestroy(c->na_copy_ev);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -1028,6 +1076,8 @@ bcts_status bcts_reset(bcts_ctx* c) {
   c->arena_pending = false;
   if (c->na_pending) (void)hipEventSynchronize(c->na_ev);
   c->na_pending = false;
+  if (c->na_copy_pending) (void)hipEventSynchronize(c->na_copy_ev);
+  c->na_copy_pending = false;
   (void)hipGetLastError();
   if (c->serve) c->serve->drop_all();
   if (c->arena) (void)hipFree(c->arena);
@@ -1275,6 +1325,55 @@ bcts_status bcts_search_batch_device(bcts_ctx* c, int32_t n, const int32_t* d_po
   if (st != BCTS_OK) return st;
   if ((st = arena_enqueued(c, s)) != BCTS_OK) return st;
   if (c->timing) return collect_timing(c);
+  return BCTS_OK;
+}
+
+bcts_status bcts_search_batch_device_noalloc(bcts_ctx* c, int32_t n, const int32_t* d_pos,
+                                             const uint8_t* d_stacks, const int32_t* depth, const int32_t* A,
+                                             float gamma, bcts_correction corr, int32_t* d_act, float* d_q,
+                                             void* hip_stream) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
+  if (!d_pos || !d_stacks || !d_act || !d_q || !depth || !A) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  for (int r = 0; r < n; ++r)
+    if ((st = validate_shape(c, A[r], depth[r], corr)) != BCTS_OK) return st;
+  if (!c->scratch) return fail(c, BCTS_E_HIP, "static scratch unavailable: %s", c->scratch_err.c_str());
+  HIPCHECK(c, hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  // The context's chunking, halved until the plan fits the scratch (results
+  // do not depend on the chunking).
+  const bool fz = c->fused && c->prec != P_FP32;
+  long long chunk = fz ? c->fused_chunk_items : c->chunk_items, tail = c->chunk_items;
+  Plan p;
+  for (;;) {
+    make_plan(p, n, depth, A, gamma, corr, kMaxA, chunk, c->prec, false, fz, c->beam, c->corr_fp32, tail);
+    if (p.total <= kScratchBytes || (chunk <= 256 && tail <= 256)) break;
+    chunk = std::max(256LL, chunk / 2);
+    tail = std::max(256LL, tail / 2);
+  }
+  if (p.total > kScratchBytes)
+    return fail(c, BCTS_E_NOMEM,
+                "search needs %zu bytes of device memory; the static scratch of the no-allocation entry point "
+                "holds %zu",
+                p.total, kScratchBytes);
+  // the host staging buffer is reused once its previous copy has finished
+  if (c->na_copy_pending) {
+    HIPCHECK(c, hipEventSynchronize(c->na_copy_ev));
+    c->na_copy_pending = false;
+  }
+  if (c->na_tables.size() < p.table_bytes) c->na_tables.resize(p.table_bytes);
+  // a search enqueued on the scratch from another stream finishes first
+  if (c->na_pending && c->na_stream != s) HIPCHECK(c, hipStreamWaitEvent(s, c->na_ev, 0));
+  if ((st = upload_tables_at(c, p, c->scratch, c->na_tables.data(), s)) != BCTS_OK) return st;
+  HIPCHECK(c, hipEventRecord(c->na_copy_ev, s));
+  c->na_copy_pending = true;
+  st = enqueue_search_at(c, p, c->scratch, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, s,
+                         false);
+  if (st != BCTS_OK) return st;
+  HIPCHECK(c, hipEventRecord(c->na_ev, s));
+  c->na_stream = s;
+  c->na_pending = true;
   return BCTS_OK;
 }
 
