@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbcts.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "expand.hip", "qnet.hip", "qnet_fused.hip", "fc.hip", "backup.hip", "mlp.hip"]
+SOURCES = ["api.hip", "plan.cpp", "expand.hip", "qnet.hip", "qnet_fused.hip", "fc.hip", "backup.hip", "mlp.hip"]
 ARCH = os.environ.get("BCTS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -25,97 +25,18 @@
 
 #include "../../include/bcts.h"
 #include "bcts_internal.h"
+#include "plan.h"
 
 using namespace bcts;
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Eq. 6 penalty coefficients: B = pen_e d_e - pen_o d_o
-void eq6_coeffs(int A, int d, double* pe, double* po) {
-  const double s = std::sqrt(std::log((double)A)), r8 = 1.0 / std::sqrt(8.0);
-  *pe = s * std::sqrt((double)d) - r8;
-  *po = s * std::sqrt((double)(d - 1)) - r8;
-}
-
-// z with Phi(z) = 1 - p (upper tail p <= 1/2), by bisection on
-// 0.5 erfc(z / sqrt 2) = p over [0, 40]; the tail function is monotone and
-// erfc keeps full relative accuracy far into the tail.
-double probit_upper_tail(double p) {
-  double lo = 0.0, hi = 40.0;
-  for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (0.5 * std::erfc(mid / std::sqrt(2.0)) > p) lo = mid; else hi = mid;
-  }
-  return 0.5 * (lo + hi);
-}
-
-// Lemma 3.2: bias of the max of n Gaussians per unit sigma
-double gev_bias(double n) {
-  if (n <= 1.0) return 0.0;
-  const double g = 0.57721566490153286060651209;
-  return g * probit_upper_tail(1.0 / (M_E * n)) + (1.0 - g) * probit_upper_tail(1.0 / n);
-}
-
-// exact gap with sigma = |delta| / sqrt 2: B = pen_e d_e - pen_o d_o
-void gev_coeffs(int A, int d, double* pe, double* po) {
-  const double no = std::pow((double)A, d - 1), ne = std::pow((double)A, d) - no;
-  *pe = gev_bias(ne) / std::sqrt(2.0);
-  *po = gev_bias(no) / std::sqrt(2.0);
-}
-
-// fused path: x3 [chunk rounded up to fc1's 256-row tiles][3136] and
-// h [chunk][512] in the operand type
-size_t fused_x3_bytes(long long chunk, int prec) {
-  const size_t el = prec == P_BF16 ? 2 : 1;
-  return align_up((size_t)(fc1_padded_rows(chunk) / kFc1Rows) * (size_t)fc1_tile_bytes((int)el));
-}
-size_t fused_workspace_bytes(long long chunk, int prec) {
-  const size_t el = prec == P_BF16 ? 2 : 1;
-  return fused_x3_bytes(chunk, prec) + (size_t)chunk * 512 * el + 256;
-}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 }  // namespace
-
-// ---------------------------------------------------------------------------
-struct Plan {
-  int n = 0, maxd = 0;
-  std::vector<RootInfo> roots;
-  std::vector<Seg> segs;
-  long long n_items = 0;
-  long long lvl_count[kMaxD + 1] = {0};
-  std::vector<int> lvl_root[kMaxD + 1];
-  std::vector<long long> lvl_start[kMaxD + 1];
-  int beam = 0;                        // beam of the cut levels (0: exhaustive)
-  long long keep_count[kMaxD + 1] = {0};   // keep-list entries of level k over all roots
-  long long chunk = 0;                 // max items of a chunk
-  bool fused = false;                  // conv stack fused per sibling group
-  std::vector<FusedGroup> groups;      // sibling groups in item order
-  struct Chunk { int g0, g1; long long i0, i1; };
-  std::vector<Chunk> chunks;           // whole groups, ~chunk_items items each
-  // The correction's own Q-network inputs (the root and depth-1 evaluations
-  // of corrected roots) can run in FP32 whatever the leaf precision: they
-  // then occupy the item range [tail_item0, n_items), evaluated by the FP32
-  // layer kernels in the ranges of tail_chunks.  tail_item0 == n_items when
-  // every item runs at the search precision.
-  long long tail_item0 = 0;
-  std::vector<std::pair<long long, long long>> tail_chunks;
-  long long tail_chunk = 0;            // max items of a tail chunk
-  size_t o_groups = 0;
-  // arena offsets
-  size_t o_root_pos = 0, o_root_stack = 0, o_roots = 0, o_segs = 0, o_V = 0, o_q0 = 0,
-         o_desc = 0, o_ws = 0, o_act = 0, o_q = 0, total = 0;
-  size_t o_pos[kMaxD + 1] = {0}, o_frames[kMaxD + 1] = {0}, o_ret[kMaxD + 1] = {0},
-         o_rew[kMaxD + 1] = {0}, o_lroot[kMaxD + 1] = {0}, o_lstart[kMaxD + 1] = {0},
-         o_keep[kMaxD + 1] = {0};
-  size_t table_bytes = 0;   // bytes of host tables uploaded (roots .. lstart)
-};
 
 struct bcts_ctx {
   int device = 0;
@@ -296,180 +217,6 @@ bcts_status validate_pos(bcts_ctx* c, int n, const int32_t* pos) {
     if (pos[i] < 0 || pos[i] >= kFrame)
       return fail(c, BCTS_E_INVAL, "root %lld: position %d outside [0,84)", i / (kSprites * 2), pos[i]);
   return BCTS_OK;
-}
-
-// Build the plan: node counts, eval segments and the arena layout.
-// `q_stride` is the row stride of out_q; `qnet_only` makes every root a
-// single root-kind eval (debug Q-network on stacks).
-// `corr_fp32` moves the root and depth-1 evaluations of corrected roots to
-// the FP32 tail (chunks of `tail_chunk_items`) when `prec` is not FP32.
-void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
-               const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
-               bool host_io, bool fused = false, int beam = 0, bool corr_fp32 = false,
-               long long tail_chunk_items = 8192) {
-  p = Plan();
-  corr_fp32 = corr_fp32 && prec != P_FP32;
-  p.beam = beam;
-  p.fused = fused && prec != P_FP32;
-  p.n = n;
-  p.roots.resize(n);
-  for (int r = 0; r < n; ++r) p.maxd = std::max(p.maxd, (int)depth[r]);
-  // level node bases (root-major inside each level)
-  for (int r = 0; r < n; ++r) {
-    RootInfo& ri = p.roots[r];
-    std::memset(&ri, 0, sizeof ri);
-    ri.A = A[r];
-    ri.d = depth[r];
-    ri.gamma_d = (float)std::pow((double)gamma, (double)ri.d);
-    ri.corr = (corr.enabled && ri.d >= 1) ? 1 : 0;
-    ri.q_stride = q_stride;
-    // nodes per level: A children of each kept node of the level above; a
-    // beam cuts levels 2..d-1 to `beam` nodes per root action where a root
-    // action's block is larger
-    ri.lcnt[0] = 1;
-    ri.kbase[0] = -1;
-    long long kept = 1;
-    for (int k = 1; k <= kMaxD; ++k) {
-      ri.kbase[k] = -1;
-      if (k <= ri.d) {
-        const long long cnt = kept * ri.A;
-        ri.lcnt[k] = cnt;
-        ri.base[k] = p.lvl_count[k];
-        p.lvl_root[k].push_back(r);
-        p.lvl_start[k].push_back(p.lvl_count[k]);
-        p.lvl_count[k] += cnt;
-        kept = cnt;
-        if (beam > 0 && k >= 2 && k <= ri.d - 1 && cnt / ri.A > beam) {
-          ri.kbase[k] = p.keep_count[k];
-          p.keep_count[k] += (long long)ri.A * beam;
-          kept = (long long)ri.A * beam;
-        }
-      } else {
-        ri.base[k] = -1;
-        ri.lcnt[k] = 0;
-      }
-    }
-    ri.leaf_blk = ri.d >= 1 ? ri.lcnt[ri.d] / ri.A : 0;
-    if (ri.corr) {
-      double pe, po;
-      if (corr.mode == BCTS_CORR_EXACT_GEV) gev_coeffs(ri.A, ri.d, &pe, &po);
-      else eq6_coeffs(ri.A, ri.d, &pe, &po);
-      ri.pen_e = (float)pe;
-      ri.pen_o = (float)po;
-    }
-  }
-  // eval segments: per root, leaves, depth-1 nodes, root (with corr_fp32 the
-  // depth-1 and root segments of corrected roots follow all the others)
-  long long item = 0;
-  // (at depth 1 the depth-1 nodes are the leaves: their values serve the
-  // Bellman errors unless those are taken in FP32, which needs A FP32 evals)
-  auto add_corr_segs = [&](int r) {
-    RootInfo& ri = p.roots[r];
-    if (ri.corr && (ri.d >= 2 || corr_fp32)) {
-      p.segs.push_back(Seg{item, r, 1, ri.A, 1});
-      ri.d1_item = item;
-      item += ri.A;
-    }
-    if (ri.corr) {
-      p.segs.push_back(Seg{item, r, 0, ri.A, 2});
-      ri.root_item = item;
-      item += 1;
-    }
-  };
-  for (int r = 0; r < n; ++r) {
-    RootInfo& ri = p.roots[r];
-    ri.leaf_item = ri.d1_item = ri.root_item = -1;
-    if (ri.d >= 1) {
-      const long long cnt = ri.lcnt[ri.d];
-      p.segs.push_back(Seg{item, r, ri.d, ri.A, 0});
-      ri.leaf_item = item;
-      item += cnt;
-    }
-    if (ri.d == 0) {                   // no search: the root eval is the result
-      p.segs.push_back(Seg{item, r, 0, ri.A, 2});
-      ri.root_item = item;
-      item += 1;
-    } else if (!corr_fp32) {
-      add_corr_segs(r);
-    }
-  }
-  const size_t main_segs = p.segs.size();
-  p.tail_item0 = item;
-  if (corr_fp32)
-    for (int r = 0; r < n; ++r)
-      if (p.roots[r].d >= 1) add_corr_segs(r);
-  p.n_items = item;
-  {
-    const long long tc = std::max(1LL, tail_chunk_items);
-    for (long long i = p.tail_item0; i < p.n_items; i += tc) {
-      const long long e = std::min(p.n_items, i + tc);
-      p.tail_chunks.emplace_back(i, e);
-      p.tail_chunk = std::max(p.tail_chunk, e - i);
-    }
-  }
-  // sibling groups: the A children of each level-(d-1) node, the A depth-1
-  // nodes of a root, a root alone; chunks hold whole groups
-  for (size_t si = 0; si < main_segs; ++si) {
-    const Seg& sg = p.segs[si];
-    const RootInfo& ri = p.roots[sg.root];
-    const long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : ri.lcnt[ri.d]);
-    const int gsz = sg.kind == 2 ? 1 : ri.A;
-    for (long long j = 0; j < cnt; j += gsz) p.groups.push_back(FusedGroup{sg.item0 + j, gsz, 0});
-  }
-  {
-    const long long target = std::max(1LL, chunk_items);
-    int g = 0;
-    p.chunk = 1;
-    while (g < (int)p.groups.size()) {
-      Plan::Chunk ch;
-      ch.g0 = g;
-      ch.i0 = p.groups[g].item0;
-      long long items = 0;
-      while (g < (int)p.groups.size() && (items == 0 || items + p.groups[g].count <= target)) {
-        items += p.groups[g].count;
-        ++g;
-      }
-      ch.g1 = g;
-      ch.i1 = ch.i0 + items;
-      p.chunk = std::max(p.chunk, items);
-      p.chunks.push_back(ch);
-    }
-  }
-
-  // arena layout
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
-  p.o_roots = take(sizeof(RootInfo) * n);
-  p.o_segs = take(sizeof(Seg) * p.segs.size());
-  p.o_groups = take(sizeof(FusedGroup) * p.groups.size());
-  for (int k = 1; k <= p.maxd; ++k) {
-    p.o_lroot[k] = take(sizeof(int) * p.lvl_root[k].size());
-    p.o_lstart[k] = take(sizeof(long long) * p.lvl_start[k].size());
-  }
-  p.table_bytes = o;
-  if (host_io) {
-    p.o_root_pos = take(sizeof(int32_t) * n * kSprites * 2);
-    p.o_root_stack = take((size_t)n * 4 * kFrameBytes);
-    p.o_act = take(sizeof(int32_t) * n);
-    p.o_q = take(sizeof(float) * (size_t)n * q_stride);
-  }
-  for (int k = 1; k <= p.maxd; ++k) {
-    p.o_pos[k] = take((size_t)p.lvl_count[k] * 16);
-    p.o_frames[k] = take((size_t)p.lvl_count[k] * kFrameBytes);
-    p.o_ret[k] = take((size_t)p.lvl_count[k] * sizeof(float));
-    p.o_rew[k] = take((size_t)p.lvl_count[k]);
-    if (p.keep_count[k] > 0) p.o_keep[k] = take(sizeof(int) * (size_t)p.keep_count[k]);
-  }
-  p.o_V = take(sizeof(float) * p.n_items);
-  p.o_q0 = take(sizeof(float) * (size_t)n * kMaxA);
-  p.o_desc = take(sizeof(ItemDesc) * std::max(p.chunk, p.tail_chunk));
-  {
-    size_t ws = p.chunks.empty() ? 0
-                : (p.fused ? fused_workspace_bytes(p.chunk, prec) : qnet_workspace_bytes(p.chunk, prec));
-    if (p.tail_chunk > 0) ws = std::max(ws, qnet_workspace_bytes(p.tail_chunk, P_FP32));
-    p.o_ws = take(ws);
-  }
-  p.total = o;
 }
 
 // Plan a search with the context's Q-network path settings.
@@ -741,18 +488,6 @@ bcts_status search_host(bcts_ctx* c, int n, const int32_t* pos, const uint8_t* s
 // arrive while others are on the GPU join the next free slot and run
 // concurrently with the batches still in flight.
 // ===========================================================================
-size_t request_bytes(int d, int A) {
-  size_t b = 0, cnt = 1;
-  for (int k = 1; k <= d; ++k) {
-    cnt *= (size_t)A;
-    b += cnt * (size_t)(kFrameBytes + 16 + 4 + 1) + 4 * kAlign;
-  }
-  const size_t items = (d >= 1 ? cnt : 0) + (d >= 2 ? (size_t)A : 0) + 1;
-  b += items * 4 + (size_t)4 * kFrameBytes + 64 + kMaxA * 4 * 2 + 4 + sizeof(RootInfo) + 3 * sizeof(Seg) +
-       kMaxD * 12 + 16 * kAlign;
-  return b;
-}
-
 struct ServeReq {
   uint64_t ticket;
   int A, d;

@@ -21,70 +21,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.h"
+
 namespace bcts {
-
-constexpr int kFrame = 84;
-constexpr int kMaxBeam = 256;           // largest beam of the pruned search
-constexpr int kFrameBytes = 84 * 84;
-constexpr int kSprites = 8;
-constexpr int kMaxA = 18;
-constexpr int kMaxD = 6;
-
-// fc1's operands (its input x3 [rows][3136] and its weights [512][3136], in
-// the operand type of eb bytes per element) are stored in stage-major tiles:
-// rows in tiles of 256, and in a tile each 64-byte K slice of all 256 rows is
-// one contiguous 16 KB block, the block fc1 streams per stage.  Byte kb of
-// row r lives at fc1_tiled_offset(r, kb, eb).  Row counts are padded to a
-// multiple of 256 (fc1 reads the padding rows and stores nothing for them).
-constexpr int kFc1Rows = 256;
-constexpr int kFc1K = 3136;
-constexpr int kFc1StageBytes = kFc1Rows * 64;
-__host__ __device__ inline long long fc1_tile_bytes(int eb) { return (long long)(kFc1K * eb / 64) * kFc1StageBytes; }
-__host__ __device__ inline long long fc1_tiled_offset(long long r, int kb, int eb) {
-  return (r / kFc1Rows) * fc1_tile_bytes(eb) + (long long)(kb >> 6) * kFc1StageBytes + (r % kFc1Rows) * 64 + (kb & 63);
-}
-inline long long fc1_padded_rows(long long n) { return (n + kFc1Rows - 1) / kFc1Rows * kFc1Rows; }
-
-// Per-root descriptor (device resident).
-struct RootInfo {
-  int A, d;
-  float gamma_d;          // gamma^d
-  float pen_e, pen_o;     // penalty B = pen_e * d_e - pen_o * d_o
-  int corr;               // correction applied (d >= 1 and enabled)
-  int q_stride;           // output row stride of out_q
-  int pad_;
-  long long base[kMaxD + 1];   // first node of this root at level k (k >= 1)
-  long long lcnt[kMaxD + 1];   // nodes of this root at level k (A^k unless a beam cuts earlier levels)
-  long long kbase[kMaxD + 1];  // level k cut by the beam: first entry of this root's keep list, else -1
-  long long leaf_blk;          // leaves per root action (A^(d-1) unless cut)
-  long long leaf_item;         // first leaf eval item (d >= 1), else -1
-  long long d1_item;           // first depth-1 eval item (corr and d >= 2, or d = 1 with FP32 correction evals), else -1
-  long long root_item;         // root eval item, else -1
-};
-
-// A run of eval items that belong to one root and one level.
-struct Seg {
-  long long item0;
-  int root, level, A, kind;    // kind: 0 leaf, 1 depth-1, 2 root
-};
 
 // One level's participating roots, sorted by first node.
 struct LevelRoots {
   const int* root;             // [cnt]
   const long long* start;      // [cnt] first node index of that root at this level
   int cnt;
-};
-
-struct EnvTables {
-  int delta[kMaxA][2];
-  int vel[kSprites - 1][2];
-};
-
-// Per-item Q-network input/outputs for one chunk of eval items.
-struct ItemDesc {
-  const uint8_t* frame[4];     // the 4 stack frames, channel 0 oldest
-  int A;                       // valid Q outputs
-  int q0_root;                 // root id whose q0 row this item fills, or -1
 };
 
 // Where frames live: level k >= 1 at level_frames[k] (node-major, 7056 B
@@ -102,14 +47,6 @@ __device__ __forceinline__ long long parent_local(const RootInfo& ri, const int*
   return ri.kbase[k - 1] >= 0 ? (long long)keep[k - 1][ri.kbase[k - 1] + i] : i;
 }
 
-// A sibling group: consecutive eval items whose stacks share channels 0..2
-// (the A children of one node, the A depth-1 nodes of a root, or one root).
-struct FusedGroup {
-  long long item0;             // first item (plan-global index)
-  int count;
-  int pad_;
-};
-
 // Arguments of the fused conv1->conv2->conv3 kernel (BF16 / FP8).
 struct FusedConvArgs {
   const FusedGroup* groups;    // groups of this chunk
@@ -124,9 +61,6 @@ struct FusedConvArgs {
   void* x3;                    // out: [chunk items][49][64] channels-last, in fc1's stage-major tiles
 };
 void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s);
-
-// Precisions (mirrors bcts_precision).
-enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
 
 // Device weights in GEMM layout W[N][K] for every precision.  K orders:
 // conv1 (c, kh, kw); conv2, conv3 (kh, kw, c); fc1 (h, w, c); fc2 (k).
@@ -202,7 +136,6 @@ void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, 
 // q0 rows.  `ws` is a workspace of qnet_workspace_bytes(chunk, prec) bytes.
 // With `ev` (6 events) the launches are bracketed: ev[0] before conv1,
 // ev[l+1] after layer l.
-size_t qnet_workspace_bytes(long long chunk, int prec);
 void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
                  void* ws, float* V, float* q0, hipStream_t s, hipEvent_t* ev = nullptr);
 

@@ -519,11 +519,6 @@ __global__ void absmax_kernel(const float* __restrict__ s, long long n, float* o
 
 }  // namespace
 
-size_t qnet_workspace_bytes(long long chunk, int prec) {
-  const size_t el = prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1;
-  return (size_t)chunk * (12800 + 5184 + 3136 + 512) * el + 256;
-}
-
 void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, int nsegs,
                       const RootInfo* roots, const FrameBases& fb, ItemDesc* out, hipStream_t s) {
   if (n_items <= 0) return;
