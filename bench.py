@@ -24,7 +24,8 @@ Two further workloads print their own JSON line:
   --workload serve  Poisson arrivals at 2000 requests/s for 60 s (A in
                     {4,6,18}, depth 1-4), BF16, continuous batching through
                     submit/progress/poll; p50/p99 request latency after a
-                    5 s warm-up, plus a run under a 1 GB device budget;
+                    5 s warm-up, plus a run under a 1 GB device budget and
+                    one at 20,000 requests/s for 10 s;
   --workload mlp    the learned forward-model world (a fully connected
                     model with three hidden layers of width 100, A = 2 and
                     10): GPU time per search of one root against depth, the
@@ -64,6 +65,8 @@ LAYER_KERNEL = {"conv1": "layer_kernel<0,P>", "conv2": "layer_kernel<1,P>", "con
 MIXED_SEED, SERVE_SEED, MLP_SEED = 1004, 1005, 1007
 # algorithmic bytes per new node written by the expansion: frame, positions, return, reward
 EXPAND_BYTES_PER_NODE = 7056 + 16 + 4 + 1
+# committed autotune results (per precision and shape) and FP8 scales
+TUNING_FILE = os.path.join(ROOT, "paper_2107_01715_amd", "tuning.json")
 
 
 def _oracle_root(args):
@@ -80,17 +83,21 @@ def _oracle_root(args):
         return r, res.q, res.action, res.ties
 
 
-def cpu_baseline(n_sample: int):
-    """The oracle as it stands on a bounded sample of roots, one process per
-    core (fork, before any GPU use)."""
+def oracle_pool():
+    """A process pool for the oracle, one worker per core (at most 16),
+    forked before any GPU use."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), 16, n_sample)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    return mp.get_context("fork").Pool(cores), cores
+
+
+def cpu_baseline(pool, cores, n_sample: int):
+    """The oracle as it stands, timed on a bounded sample of roots."""
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        out = pool.map(_oracle_root, [(r,) for r in range(n_sample)])
+    out = pool.map(_oracle_root, [(r,) for r in range(n_sample)])
     dt = time.perf_counter() - t0
     leaves = n_sample * A ** DEPTH
-    return {"value": leaves / dt, "unit": "leaf evals/s", "cores": cores, "kind": "oracle",
+    return {"value": leaves / dt, "unit": "leaf evals/s", "cores": min(cores, n_sample), "kind": "oracle",
             "sample": f"{n_sample} roots of the A=18,d=3 workload ({leaves} leaves), FP64, "
                       f"{dt:.1f} s wall"}, {r: (q, a, t) for r, q, a, t in out}
 
@@ -252,6 +259,7 @@ def _serve_once(args, budget, duration, warm, rate):
                     lat[j] = r[2] - (t0 + t_arr[j])
                     del pending[tk]
     wall = time.monotonic() - t0
+    stats = ctx.serve_stats()
     ctx.close()
     sel = t_arr >= warm
     lm = lat[sel] * 1e3
@@ -260,7 +268,8 @@ def _serve_once(args, budget, duration, warm, rate):
             "p50_ms": float(np.percentile(lm, 50)), "p99_ms": float(np.percentile(lm, 99)),
             "mean_ms": float(lm.mean()), "max_ms": float(lm.max()),
             "requests_per_s": float(n / wall), "leaf_evals_per_s": float(leaves.sum() / wall),
-            "max_pending": int(max_pending),
+            "max_pending": int(max_pending), "cohorts": stats["cohorts_done"],
+            "requests_per_cohort": float(n / max(stats["cohorts_done"], 1)),
             "budget_bytes": budget if budget else "80% of free device memory"}
 
 
@@ -270,6 +279,10 @@ def run_serve(args):
     print(f"# serve (default budget): {main_run}", file=sys.stderr, flush=True)
     small = _serve_once(args, 1 << 30, min(duration, 20.0), min(warm, 5.0), rate)
     print(f"# serve (1 GB budget): {small}", file=sys.stderr, flush=True)
+    # ten times the arrival rate, where batching and admission bind
+    heavy = _serve_once(args, 0, min(duration, 10.0), min(warm, 2.0), 10 * rate)
+    heavy["offered_requests_per_s"] = 10 * rate
+    print(f"# serve (10x rate): {heavy}", file=sys.stderr, flush=True)
     out = {
         "metric": "serving request latency p50/p99 (Poisson 2000 req/s)", "value": main_run["p99_ms"],
         "unit": "ms (p99)", "n_gpus": 1, "steps": main_run["requests"], "warmup": 0,
@@ -279,7 +292,7 @@ def run_serve(args):
         "config": {"workload": f"Poisson arrivals 2000 req/s for {duration:g} s; A ~ U{{4,6,18}}, depth 1-4 "
                                "(p .50/.30/.15/.05, A=18 caps at 3); gamma 0.99, BCTS c=1.0; latency = completion "
                                f"- arrival after a {warm:g} s warm-up", "precision": args.precision},
-        "serve": main_run, "serve_1gb_budget": small,
+        "serve": main_run, "serve_1gb_budget": small, "serve_10x_rate": heavy,
     }
     print(json.dumps(out))
 
@@ -454,9 +467,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=64, help="roots timed through the oracle (0 = skip)")
+    ap.add_argument("--oracle-all", type=int, default=1,
+                    help="1 = also run the oracle (untimed) on the remaining roots, for agreement over all 256")
     ap.add_argument("--skip-fp32-single", action="store_true")
-    ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", "/tmp/bcts_autotune.json"))
-    ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--tune-cache", default=os.environ.get("BCTS_TUNE_CACHE", TUNING_FILE),
+                    help="autotune results and FP8 scales (JSON); read unless --retune")
+    ap.add_argument("--retune", action="store_true", help="autotune and calibrate again, write --tune-out")
+    ap.add_argument("--tune-out", default=None, help="where --retune writes (default: --tune-cache)")
     ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve", "mlp", "beam", "copy"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--quick", action="store_true",
@@ -477,10 +494,14 @@ def main():
     if args.workload == "copy":
         return run_copy(args)
 
-    # CPU baseline first: the worker pool forks before the GPU is touched
-    cpu, oracle_ref = (None, {})
+    # CPU baseline first: the worker pool forks before the GPU is touched; it
+    # stays open to run the oracle over the remaining roots (untimed) after
+    # the GPU measurements
+    cpu, oracle_ref, pool = None, {}, None
+    if args.cpu_sample > 0 or args.oracle_all:
+        pool, cores = oracle_pool()
     if args.cpu_sample > 0:
-        cpu, oracle_ref = cpu_baseline(args.cpu_sample)
+        cpu, oracle_ref = cpu_baseline(pool, cores, args.cpu_sample)
         print(f"# cpu baseline: {cpu['value']:.1f} leaf evals/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     import numpy as np
@@ -493,7 +514,16 @@ def main():
     ctx = bcts.Context(0)
     ctx.set_env(ep.delta, ep.vel)
     ctx.set_qnet(W.qnet_blob(W.qnet_weights(WEIGHT_SEED)))
-    ctx.calibrate_fp8(cal)
+    cache = {}
+    try:
+        cache = json.load(open(args.tune_cache))
+    except (OSError, ValueError):
+        pass
+    if "fp8_scales" in cache and not args.retune:
+        ctx.set_fp8_scales(np.asarray(cache["fp8_scales"], np.float32))
+    else:
+        ctx.calibrate_fp8(cal)
+        cache["fp8_scales"] = [float(v) for v in ctx.get_fp8_scales()]
     corr = bcts.correction(True, C)
     dev = torch.device("cuda:0")
     pos_t = torch.from_numpy(pos).to(dev)
@@ -533,11 +563,6 @@ def main():
             continue
         ctx.set_precision(prec_id[prec])
         key = f"{prec}:{N_ROOTS}x{A}^{DEPTH}"
-        cache = {}
-        try:
-            cache = json.load(open(args.tune_cache))
-        except (OSError, ValueError):
-            pass
         if key in cache and not args.retune:
             best = cache[key]
             ctx.set_tuning(bcts.TUNE_FUSED, best["fused"])
@@ -547,15 +572,18 @@ def main():
             with torch.cuda.stream(stream):
                 best = ctx.autotune(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, reps=2, stream=stream)
             torch.cuda.synchronize()
-            cache[key] = best
-            try:
-                json.dump(cache, open(args.tune_cache, "w"))
-            except OSError:
-                pass
+            cache[key] = {k: int(best[k]) for k in ("fused", "round", "chunk")}
+            cache[key]["us_per_search"] = best.get("us_per_search")
         tuned_all[prec] = {k: best[k] for k in ("fused", "round", "chunk")}
         tuned_all[prec]["us_per_search"] = best.get("us_per_search")
         print(f"# autotune {prec}: {best}", file=sys.stderr, flush=True)
     tuned = tuned_all.get(args.precision, {})
+    if args.retune:
+        try:
+            with open(args.tune_out or args.tune_cache, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError as e:
+            print(f"# could not write the tuning file: {e}", file=sys.stderr)
 
     def set_prec(prec):
         ctx.set_precision(prec_id[prec])
@@ -566,7 +594,12 @@ def main():
             ctx.set_tuning(bcts.TUNE_FUSED_CHUNK, t["chunk"])
 
     print(f"# {args.precision} batched: warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
-    wall, per_step, kern, act_main, q_main = batched(args.precision, args.steps, args.warmup)
+    # per-kernel HIP-event timing (each step waits for its events) ...
+    wall_ev, per_step, kern, act_main, q_main = batched(args.precision, args.steps, args.warmup)
+    # ... and the headline: the same steps back to back, the host planning
+    # step i+1 while the device runs step i; synchronised before and after
+    wall, _, _, act_bb, q_bb = batched(args.precision, args.steps, 1, timed=False)
+    assert np.array_equal(act_bb, act_main) and np.array_equal(q_bb, q_main)
     ms_step = wall / args.steps * 1e3
     value = leaves / (wall / args.steps)
 
@@ -618,7 +651,19 @@ def main():
                                                          np.array_equal(hq, q_main[:, :A]))}
         print(f"# {args.precision} host buffers: {host_form['value']:.4g} leaf evals/s", file=sys.stderr, flush=True)
 
-    # accuracy: vs FP64 oracle on the sample, vs FP32 GPU path on all roots
+    # the oracle on the roots the timed sample left out (untimed): agreement
+    # over all 256 roots
+    if pool is not None and args.oracle_all and not args.quick:
+        rest = [(r,) for r in range(N_ROOTS) if r not in oracle_ref]
+        t0 = time.perf_counter()
+        for r, q_, a_, t_ in pool.map(_oracle_root, rest):
+            oracle_ref[r] = (q_, a_, t_)
+        print(f"# oracle on {len(rest)} more roots: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    if pool is not None:
+        pool.close()
+        pool.join()
+
+    # accuracy: vs FP64 oracle, vs FP32 GPU path on all roots
     accuracy = {}
     if "fp32" not in results:
         results["fp32"] = results[args.precision]
@@ -680,6 +725,10 @@ def main():
                    "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "whole-batch search latency per step (HIP events)"},
+        "ms_per_step_event_timed": wall_ev / args.steps * 1e3,
+        "timing": "value and ms_per_step: steps back to back (the host plans the next step while the device runs "
+                  "the current one), synchronised before and after; kernel times and latency: a second pass whose "
+                  "every step waits for its HIP events",
         "precisions": {p: {"value": results[p][0]} for p in results},
         "fp32_single_root": single,
         "host_buffers": host_form,

@@ -234,28 +234,50 @@ bcts_status bcts_autotune(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos, 
                           void* d_scratch_action, void* d_scratch_q, int32_t reps, void* hip_stream,
                           int64_t* out_best);
 
-/* ---- serving: continuous batching with HBM-budget admission ------------ */
-/* Queue one request (host buffers copied).  Returns a ticket.  Requests
- * whose own minimal footprint exceeds the budget fail with BCTS_E_NOMEM.   */
+/* ---- serving: iteration-level continuous batching, pooled HBM admission --- */
+/* The paper selects one action per tree search (Alg. 1); a server answers
+ * many such requests at once.  The engine works in steps on its own stream:
+ * before a step it admits queued requests, in arrival order, as a cohort
+ * (planned as one batch) while its device memory pool and pinned staging
+ * hold the cohort's plan; the step then advances every admitted cohort by
+ * one stage of its search -- upload and level 1, each further level, each
+ * Q-network chunk, the FP32 correction evaluations, backup and the copy of
+ * its results -- or, for a light cohort (at most 32,768 nodes plus eval
+ * items), by all of them.  A request that arrives while a large search runs
+ * joins at the next stage boundary.  All cohorts share one memory pool
+ * (what the HBM budget leaves beyond the weights, the work arena and the
+ * shared Q-network workspace, capped at 16 GiB); a cohort's range returns to
+ * the pool when its last stage has finished.  Results do not depend on how
+ * requests were batched: each equals the same root searched alone, bit for
+ * bit. */
+/* Queue one request (host buffers copied).  Returns a ticket.  A request
+ * whose own plan exceeds the serving pool fails with BCTS_E_NOMEM.         */
 bcts_status bcts_submit(bcts_ctx* ctx, const int32_t* pos, const uint8_t* stack, int32_t depth,
                         int32_t A, float gamma, bcts_correction corr, uint64_t* ticket);
-/* Advance the engine without blocking: retire finished batches, admit
- * queued requests in arrival order while the budget allows, launch them.
- * Returns the number of requests still pending in *pending.               */
+/* Advance the engine without blocking: retire finished steps and cohorts,
+ * admit queued requests while the pools allow, enqueue up to max_inflight
+ * steps.  *pending = requests queued or admitted and not yet finished.     */
 bcts_status bcts_progress(bcts_ctx* ctx, int32_t* pending);
 /* Result of a ticket: BCTS_OK (copied out, ticket released), BCTS_E_BUSY
  * (not finished), BCTS_E_STATE (unknown ticket).  q has room for A floats;
  * t_done is the host monotonic time (s) at which completion was observed.  */
 bcts_status bcts_poll(bcts_ctx* ctx, uint64_t ticket, int32_t* action, float* q, double* t_done);
-/* Serving limits: max requests per engine batch, max batches in flight.   */
+/* Serving limits: max requests admitted into one cohort, max engine steps in
+ * flight (1..8).  Refused with BCTS_E_STATE while tickets are outstanding. */
 bcts_status bcts_serve_config(bcts_ctx* ctx, int32_t max_batch, int32_t max_inflight);
-/* While requests are queued or batches are in flight (finished results
- * waiting for bcts_poll do not count), the calls that change what those
- * batches read -- bcts_set_env, bcts_set_qnet, bcts_set_precision,
- * bcts_set_fp8_scales, bcts_calibrate_fp8, bcts_set_tuning, bcts_set_beam,
- * bcts_autotune -- return BCTS_E_STATE and change nothing; drive
- * bcts_progress until it reports nothing pending first.                    */
-/* Device bytes one request of (depth, A) reserves while admitted.         */
+/* Engine state (host view, as of the last bcts_progress): out[0] queued
+ * requests, [1] admitted requests not finished, [2] admitted cohorts,
+ * [3] cohorts with stages not yet enqueued, [4] steps in flight, [5] pool
+ * bytes in use, [6] pool capacity, [7] cohorts finished so far.           */
+bcts_status bcts_serve_stats(bcts_ctx* ctx, int64_t* out8);
+/* While requests are queued or admitted (finished results waiting for
+ * bcts_poll do not count), the calls that change what they read --
+ * bcts_set_env, bcts_set_qnet, bcts_set_precision, bcts_set_fp8_scales,
+ * bcts_calibrate_fp8, bcts_set_tuning, bcts_set_beam, bcts_autotune --
+ * return BCTS_E_STATE and change nothing; drive bcts_progress until it
+ * reports nothing pending first.                                           */
+/* Device bytes one request of (depth, A) takes while admitted alone (its
+ * levels, tables and values; the shared Q-network workspace aside).       */
 size_t bcts_request_bytes(int32_t depth, int32_t A);
 
 /* ---- pruned search ------------------------------------------------------ */
@@ -310,6 +332,15 @@ bcts_status bcts_mlp_search_device(bcts_ctx* ctx, int32_t n_roots, const float* 
 bcts_status bcts_debug_expand(bcts_ctx* ctx, const int32_t* pos, const uint8_t* stack,
                               int32_t depth, int32_t A, int32_t* out_pos, uint8_t* out_frames,
                               int32_t* out_reward);
+/* Failure injection (tests of the error path): the next `count` stage
+ * launches of any search or serving step fail from the host before anything
+ * of theirs is enqueued, as a failed launch would: the call returns
+ * BCTS_E_HIP and the context enters the error state (every call but
+ * bcts_reset, bcts_destroy and bcts_last_error then returns BCTS_E_STATE;
+ * queued and admitted serving requests are dropped by bcts_reset).  Work
+ * already enqueued runs to completion.                                     */
+bcts_status bcts_debug_fail_launches(bcts_ctx* ctx, int32_t count);
+
 /* Q-network on n host stacks at the current precision: out_q float [n][A]. */
 bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
                             float* out_q);

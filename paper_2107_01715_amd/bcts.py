@@ -41,7 +41,8 @@ EXPORTS = (
     "bcts_debug_expand", "bcts_debug_qnet", "bcts_set_timing", "bcts_get_timing",
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
     "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
-    "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc",
+    "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc", "bcts_serve_stats",
+    "bcts_debug_fail_launches",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32 = 0, 1, 2, 3, 4
 
@@ -90,6 +91,8 @@ _submit = _sig("bcts_submit", c_int32, _P, _P, _P, c_int32, c_int32, c_float, Co
 _progress = _sig("bcts_progress", c_int32, _P, POINTER(c_int32))
 _poll = _sig("bcts_poll", c_int32, _P, c_uint64, POINTER(c_int32), _P, POINTER(c_double))
 _serve_config = _sig("bcts_serve_config", c_int32, _P, c_int32, c_int32)
+_serve_stats = _sig("bcts_serve_stats", c_int32, _P, _P)
+_debug_fail_launches = _sig("bcts_debug_fail_launches", c_int32, _P, c_int32)
 _request_bytes = _sig("bcts_request_bytes", c_size_t, c_int32, c_int32)
 _debug_expand = _sig("bcts_debug_expand", c_int32, _P, _P, _P, c_int32, c_int32, _P, _P, _P)
 _debug_qnet = _sig("bcts_debug_qnet", c_int32, _P, c_int32, _P, c_int32, _P)
@@ -272,6 +275,18 @@ def bcts_poll(ctx, ticket: int, A: int):
 
 def bcts_serve_config(ctx, max_batch: int, max_inflight: int):
     _check(ctx, _serve_config(ctx, max_batch, max_inflight))
+
+
+def bcts_serve_stats(ctx) -> dict:
+    out = np.zeros(8, dtype=np.int64)
+    _check(ctx, _serve_stats(ctx, _ptr(out)))
+    keys = ("queued", "admitted", "cohorts", "staging", "steps_in_flight", "pool_in_use", "pool_capacity",
+            "cohorts_done")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def bcts_debug_fail_launches(ctx, count: int):
+    _check(ctx, _debug_fail_launches(ctx, count))
 
 
 def bcts_request_bytes(depth: int, A: int) -> int:

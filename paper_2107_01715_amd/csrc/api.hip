@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -98,6 +99,8 @@ struct bcts_ctx {
   double t_ms[24] = {0};
   // serving
   struct ServeEngine* serve = nullptr;
+  // launches still to fail on purpose (bcts_debug_fail_launches)
+  int inject_fail = 0;
   // learned forward-model world
   void* mlp_mem = nullptr;
   MlpDev mlp{};
@@ -283,69 +286,154 @@ bcts_status ensure_events(bcts_ctx* c, size_t n) {
   return BCTS_OK;
 }
 
-// Q-network over every eval item of the plan, chunk by chunk.  With `ev`
-// (6 events per chunk) the launches of each chunk are bracketed.
-bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameBases& fb, hipStream_t s,
-                               hipEvent_t* ev) {
+// ---- the launch sequence of a planned search, stage by stage -------------
+// A stage is a bounded unit of one search's device work: one level of the
+// expansion, one Q-network chunk, the FP32 correction evaluations, or the
+// backup.  `A` is the base of the search's arena (the plan's offsets), `desc`
+// and `ws` the item descriptors and Q-network workspace the Q-network stages
+// use (the arena's own, or a region several searches on one stream share).
+// Every stage first passes launch_gate, which lets a test make the next
+// launches fail from the host.
+bcts_status launch_gate(bcts_ctx* c) {
+  if (c->inject_fail > 0) {
+    --c->inject_fail;
+    return fail(c, BCTS_E_HIP, "injected launch failure (bcts_debug_fail_launches)");
+  }
+  return BCTS_OK;
+}
+
+FrameBases frame_bases(const Plan& p, char* A, const uint8_t* d_stacks) {
+  FrameBases fb{};
+  fb.level_frames[0] = d_stacks;
+  for (int k = 1; k <= p.maxd; ++k) {
+    fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
+    fb.keep[k] = p.keep_count[k] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k]) : nullptr;
+  }
+  return fb;
+}
+
+// Level k of the expansion (and its beam cut).
+bcts_status enqueue_level(bcts_ctx* c, const Plan& p, char* A, int k, const int32_t* d_pos, float gamma,
+                          hipStream_t s) {
+  bcts_status st = launch_gate(c);
+  if (st != BCTS_OK) return st;
   const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
-  ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
+  const float g = (float)std::pow((double)gamma, (double)(k - 1));
+  LevelRoots lr{reinterpret_cast<const int*>(A + p.o_lroot[k]), reinterpret_cast<const long long*>(A + p.o_lstart[k]),
+                (int)p.lvl_root[k].size()};
+  launch_expand(k, p.lvl_count[k], lr, roots, d_pos,
+                k > 1 ? reinterpret_cast<const uint8_t*>(A + p.o_pos[k - 1]) : nullptr,
+                k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr,
+                k > 1 && p.keep_count[k - 1] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k - 1]) : nullptr,
+                c->env, g, reinterpret_cast<uint8_t*>(A + p.o_pos[k]), reinterpret_cast<uint8_t*>(A + p.o_frames[k]),
+                reinterpret_cast<float*>(A + p.o_ret[k]), reinterpret_cast<uint8_t*>(A + p.o_rew[k]), s);
+  if (p.keep_count[k] > 0)
+    launch_prune(k, (int)p.lvl_root[k].size(), lr, roots, reinterpret_cast<const float*>(A + p.o_ret[k]),
+                 reinterpret_cast<int*>(A + p.o_keep[k]), p.beam, s);
+  return BCTS_OK;
+}
+
+// Q-network chunk ci of the plan.  With `cev` (6 events) its launches are
+// bracketed.
+bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* desc, char* ws, const FrameBases& fb,
+                               int ci, hipStream_t s, hipEvent_t* cev) {
+  bcts_status st = launch_gate(c);
+  if (st != BCTS_OK) return st;
+  const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
   float* V = reinterpret_cast<float*>(A + p.o_V);
   float* q0 = reinterpret_cast<float*>(A + p.o_q0);
-  const int nchunks = (int)p.chunks.size();
   const FusedGroup* groups = reinterpret_cast<const FusedGroup*>(A + p.o_groups);
-  for (int ci = 0; ci < nchunks; ++ci) {
-    const Plan::Chunk& ch = p.chunks[ci];
-    const long long cnt = ch.i1 - ch.i0;
-    hipEvent_t* cev = ev ? ev + 6 * ci : nullptr;
-    launch_item_desc(ch.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
-    if (!p.fused) {
-      launch_qnet(c->prec, c->q, desc, cnt, A + p.o_ws, V + ch.i0, q0, s, cev);
-      continue;
-    }
-    const QnetDev& q = c->q;
-    FusedConvArgs fa{};
-    fa.groups = groups + ch.g0;
-    fa.item_base = ch.i0;
-    fa.desc = desc;
-    const bool f8 = c->prec == P_FP8;
-    for (int l = 0; l < 3; ++l) {
-      // conv1 in GEMM layout, conv2 / conv3 fragment-major
-      fa.w[l] = l == 0 ? (f8 ? (const void*)q.w8[0] : (const void*)q.wb[0]) : (f8 ? q.wf8[l] : q.wfb[l]);
-      fa.bias[l] = q.b[l];
-      fa.acc_scale[l] = f8 ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
-      fa.out_s8[l] = f8 ? q.ascale[l + 1] : 1.f;
-    }
-    fa.acc_scale[0] /= 255.f;
-    fa.pix_s8 = f8 ? q.ascale[0] : 1.f;
-    char* x3 = A + p.o_ws;
-    char* h = x3 + fused_x3_bytes(p.chunk, c->prec);
-    fa.x3 = x3;
-    if (cev) HIPCHECK(c, hipEventRecord(cev[0], s));
-    launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s);
-    if (cev) {
-      HIPCHECK(c, hipEventRecord(cev[1], s));
-      HIPCHECK(c, hipEventRecord(cev[2], s));
-      HIPCHECK(c, hipEventRecord(cev[3], s));
-    }
-    launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr);
-    if (cev) HIPCHECK(c, hipEventRecord(cev[5], s));
+  const Plan::Chunk& ch = p.chunks[ci];
+  const long long cnt = ch.i1 - ch.i0;
+  launch_item_desc(ch.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
+  if (!p.fused) {
+    launch_qnet(c->prec, c->q, desc, cnt, ws, V + ch.i0, q0, s, cev);
+    return BCTS_OK;
   }
-  // the correction's root and depth-1 evaluations in FP32 (layer kernels)
-  if (ev && !p.tail_chunks.empty()) HIPCHECK(c, hipEventRecord(ev[6 * nchunks], s));
+  const QnetDev& q = c->q;
+  FusedConvArgs fa{};
+  fa.groups = groups + ch.g0;
+  fa.item_base = ch.i0;
+  fa.desc = desc;
+  const bool f8 = c->prec == P_FP8;
+  for (int l = 0; l < 3; ++l) {
+    // conv1 in GEMM layout, conv2 / conv3 fragment-major
+    fa.w[l] = l == 0 ? (f8 ? (const void*)q.w8[0] : (const void*)q.wb[0]) : (f8 ? q.wf8[l] : q.wfb[l]);
+    fa.bias[l] = q.b[l];
+    fa.acc_scale[l] = f8 ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
+    fa.out_s8[l] = f8 ? q.ascale[l + 1] : 1.f;
+  }
+  fa.acc_scale[0] /= 255.f;
+  fa.pix_s8 = f8 ? q.ascale[0] : 1.f;
+  char* x3 = ws;
+  char* h = x3 + fused_x3_bytes(p.chunk, c->prec);
+  fa.x3 = x3;
+  if (cev) HIPCHECK(c, hipEventRecord(cev[0], s));
+  launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s);
+  if (cev) {
+    HIPCHECK(c, hipEventRecord(cev[1], s));
+    HIPCHECK(c, hipEventRecord(cev[2], s));
+    HIPCHECK(c, hipEventRecord(cev[3], s));
+  }
+  launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr);
+  if (cev) HIPCHECK(c, hipEventRecord(cev[5], s));
+  return BCTS_OK;
+}
+
+// The correction's root and depth-1 evaluations in FP32 (layer kernels).
+bcts_status enqueue_tail(bcts_ctx* c, const Plan& p, char* A, ItemDesc* desc, char* ws, const FrameBases& fb,
+                         hipStream_t s) {
+  if (p.tail_chunks.empty()) return BCTS_OK;
+  bcts_status st = launch_gate(c);
+  if (st != BCTS_OK) return st;
+  const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
+  float* V = reinterpret_cast<float*>(A + p.o_V);
+  float* q0 = reinterpret_cast<float*>(A + p.o_q0);
   for (const auto& tc : p.tail_chunks) {
     const long long cnt = tc.second - tc.first;
     launch_item_desc(tc.first, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc,
                      s);
-    launch_qnet(P_FP32, c->q, desc, cnt, A + p.o_ws, V + tc.first, q0, s, nullptr);
+    launch_qnet(P_FP32, c->q, desc, cnt, ws, V + tc.first, q0, s, nullptr);
   }
+  return BCTS_OK;
+}
+
+// Backup, correction and root action into d_act / d_q.
+bcts_status enqueue_backup(bcts_ctx* c, const Plan& p, char* A, float gamma, float corr_scale, int32_t* d_act,
+                           float* d_q, hipStream_t s) {
+  bcts_status st = launch_gate(c);
+  if (st != BCTS_OK) return st;
+  LevelRet lr{};
+  for (int k = 1; k <= p.maxd; ++k) lr.ret[k] = reinterpret_cast<const float*>(A + p.o_ret[k]);
+  launch_backup_correct(p.n, reinterpret_cast<const RootInfo*>(A + p.o_roots), reinterpret_cast<float*>(A + p.o_V),
+                        reinterpret_cast<float*>(A + p.o_q0), lr, gamma, corr_scale, d_act, d_q, s);
+  return BCTS_OK;
+}
+
+// Q-network over every eval item of the plan, chunk by chunk, then the FP32
+// correction evaluations.  With `ev` (6 events per chunk, then 2 around the
+// FP32 evaluations) the launches are bracketed.
+bcts_status enqueue_qnet_stage(bcts_ctx* c, const Plan& p, char* A, const FrameBases& fb, hipStream_t s,
+                               hipEvent_t* ev) {
+  ItemDesc* desc = reinterpret_cast<ItemDesc*>(A + p.o_desc);
+  char* ws = A + p.o_ws;
+  const int nchunks = (int)p.chunks.size();
+  for (int ci = 0; ci < nchunks; ++ci) {
+    const bcts_status st = enqueue_qnet_chunk(c, p, A, desc, ws, fb, ci, s, ev ? ev + 6 * ci : nullptr);
+    if (st != BCTS_OK) return st;
+  }
+  if (ev && !p.tail_chunks.empty()) HIPCHECK(c, hipEventRecord(ev[6 * nchunks], s));
+  const bcts_status st = enqueue_tail(c, p, A, desc, ws, fb, s);
+  if (st != BCTS_OK) return st;
   if (ev && !p.tail_chunks.empty()) HIPCHECK(c, hipEventRecord(ev[6 * nchunks + 1], s));
   return BCTS_OK;
 }
 
+// Enqueue the whole search (every stage, in order).  Root inputs and
+// outputs are device pointers.
 bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t* d_pos,
                               const uint8_t* d_stacks, float gamma, float corr_scale, int32_t* d_act,
                               float* d_q, hipStream_t s, bool timed) {
-  const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
   const int nchunks = (int)p.chunks.size();
   hipEvent_t* ev = nullptr;
   if (timed) {
@@ -361,39 +449,15 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
     for (int k = 1; k <= p.maxd; ++k) c->t_nodes += p.lvl_count[k];
     HIPCHECK(c, hipEventRecord(ev[0], s));
   }
-  double g = 1.0;
+  bcts_status st;
   for (int k = 1; k <= p.maxd; ++k) {
-    LevelRoots lr{reinterpret_cast<const int*>(A + p.o_lroot[k]),
-                  reinterpret_cast<const long long*>(A + p.o_lstart[k]), (int)p.lvl_root[k].size()};
-    launch_expand(k, p.lvl_count[k], lr, roots, d_pos,
-                  k > 1 ? reinterpret_cast<const uint8_t*>(A + p.o_pos[k - 1]) : nullptr,
-                  k > 1 ? reinterpret_cast<const float*>(A + p.o_ret[k - 1]) : nullptr,
-                  k > 1 && p.keep_count[k - 1] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k - 1]) : nullptr,
-                  c->env, (float)g,
-                  reinterpret_cast<uint8_t*>(A + p.o_pos[k]), reinterpret_cast<uint8_t*>(A + p.o_frames[k]),
-                  reinterpret_cast<float*>(A + p.o_ret[k]), reinterpret_cast<uint8_t*>(A + p.o_rew[k]), s);
-    if (p.keep_count[k] > 0)
-      launch_prune(k, (int)p.lvl_root[k].size(), lr, roots, reinterpret_cast<const float*>(A + p.o_ret[k]),
-                   reinterpret_cast<int*>(A + p.o_keep[k]), p.beam, s);
+    if ((st = enqueue_level(c, p, A, k, d_pos, gamma, s)) != BCTS_OK) return st;
     if (timed) HIPCHECK(c, hipEventRecord(ev[k], s));
-    g *= gamma;
   }
-  FrameBases fb{};
-  fb.level_frames[0] = d_stacks;
-  for (int k = 1; k <= p.maxd; ++k) {
-    fb.level_frames[k] = reinterpret_cast<const uint8_t*>(A + p.o_frames[k]);
-    fb.keep[k] = p.keep_count[k] > 0 ? reinterpret_cast<const int*>(A + p.o_keep[k]) : nullptr;
-  }
-  float* V = reinterpret_cast<float*>(A + p.o_V);
-  float* q0 = reinterpret_cast<float*>(A + p.o_q0);
-  {
-    bcts_status st = enqueue_qnet_stage(c, p, A, fb, s, timed ? ev + 1 + p.maxd : nullptr);
-    if (st != BCTS_OK) return st;
-  }
+  const FrameBases fb = frame_bases(p, A, d_stacks);
+  if ((st = enqueue_qnet_stage(c, p, A, fb, s, timed ? ev + 1 + p.maxd : nullptr)) != BCTS_OK) return st;
   if (timed) HIPCHECK(c, hipEventRecord(ev[3 + p.maxd + 6 * nchunks], s));
-  LevelRet lr{};
-  for (int k = 1; k <= p.maxd; ++k) lr.ret[k] = reinterpret_cast<const float*>(A + p.o_ret[k]);
-  launch_backup_correct(p.n, roots, V, q0, lr, gamma, corr_scale, d_act, d_q, s);
+  if ((st = enqueue_backup(c, p, A, gamma, corr_scale, d_act, d_q, s)) != BCTS_OK) return st;
   if (timed) HIPCHECK(c, hipEventRecord(ev[4 + p.maxd + 6 * nchunks], s));
   HIPCHECK(c, hipGetLastError());
   return BCTS_OK;
@@ -478,15 +542,24 @@ bcts_status search_host(bcts_ctx* c, int n, const int32_t* pos, const uint8_t* s
 
 
 // ===========================================================================
-// Serving: continuous batching with HBM-budget admission.
+// Serving: iteration-level continuous batching with pooled HBM admission.
 //
-// Requests are queued on submit (inputs copied).  Up to `max_inflight`
-// batches run at once, each on its own stream with its own device arena and
-// pinned staging; a batch is the longest FIFO prefix of the queue that shares
-// (gamma, correction), fits the slot's memory and has at most `max_batch`
-// requests.  Whenever a batch completes its slot is refilled, so requests that
-// arrive while others are on the GPU join the next free slot and run
-// concurrently with the batches still in flight.
+// Requests queue on bcts_submit.  The engine runs in steps, all on its own
+// stream.  Before a step it admits queued requests, in arrival order, as a
+// new cohort (the requests admitted together, planned as one batch) while
+// the memory pool and the pinned staging pool hold its plan; then the step
+// advances every admitted cohort by one stage of its search -- its upload
+// and level 1, each further level, each Q-network chunk, the FP32 correction
+// evaluations, the backup with the copy of its results to the host.  A light
+// cohort (few nodes and items) runs all its stages in one step.  A request
+// that arrives while a large search runs therefore joins at the next stage
+// boundary and completes after a few steps, not after that search.
+// Every cohort's device memory is one range of a single pool; the range
+// returns to the pool when the step holding the cohort's last stage has
+// finished on the device.  The Q-network stages of all cohorts share one
+// descriptor and workspace region: they run on one stream, one at a time.
+// Up to `max_steps` steps are in flight; the host plans and stages the next
+// step while the device runs the previous one.
 // ===========================================================================
 struct ServeReq {
   uint64_t ticket;
@@ -495,7 +568,6 @@ struct ServeReq {
   bcts_correction corr;
   int32_t pos[kSprites * 2];
   std::vector<uint8_t> stack;
-  size_t bytes;
 };
 
 struct ServeResult {
@@ -505,26 +577,48 @@ struct ServeResult {
   double t_done;
 };
 
-struct ServeSlot {
-  hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
-  char* arena = nullptr;
-  size_t arena_bytes = 0;
-  char* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  bool busy = false;
+struct Cohort {
   std::vector<uint64_t> tickets;
   std::vector<int> A;
-  size_t h_act = 0, h_q = 0;   // output offsets in pinned
+  float gamma = 1.f;
+  bcts_correction corr{};
+  Plan p;
+  size_t dev_off = 0, pin_off = 0, pin_bytes = 0;
+  size_t h_pos = 0, h_stack = 0, h_act = 0, h_q = 0;   // offsets inside its pinned range
+  int n_stages = 0, next = 0;     // stages: levels 1..maxd, chunks, FP32 tail (if any), backup
+  bool light = false;             // all stages in one step
+  uint64_t last_step = 0;         // step holding its last stage (valid once next == n_stages)
 };
 
 struct ServeEngine {
   bcts_ctx* c;
-  int max_batch = 512, max_inflight = 2;
-  long long chunk = 2048;
-  size_t slot_cap = 0;
+  int max_batch = 512, max_steps = 2;
+  long long layer_chunk = 2048;              // stacks per Q-network chunk (layer path; fused: 8x)
+  static constexpr size_t kPoolCap = (size_t)16 << 30;     // device pool cap (bytes)
+  static constexpr size_t kPinnedBytes = (size_t)96 << 20; // pinned staging pool
+  static constexpr long long kCohortLeaves = 1 << 19;      // leaves admitted into one cohort, at most
+  static constexpr long long kLightWork = 32768;           // nodes + items of a light cohort
+  bool ready = false;
+  struct Settings {
+    int prec, fused, T, corr_fp32, beam;
+    long long fchunk, lchunk;
+    bool operator==(const Settings& o) const {
+      return prec == o.prec && fused == o.fused && T == o.T && corr_fp32 == o.corr_fp32 && beam == o.beam &&
+             fchunk == o.fchunk && lchunk == o.lchunk;
+    }
+  } cfg{};
+  uint64_t cohorts_done = 0, requests_done = 0;
+  hipStream_t stream = nullptr;
+  char* dev = nullptr;          // [shared desc + workspace | pool]
+  size_t dev_bytes = 0, shared_bytes = 0;
+  RangePool pool, pin_pool;
+  char* pinned = nullptr;
   std::deque<ServeReq> queue;
-  std::vector<ServeSlot> slots;
+  std::list<Cohort> active;
+  struct Step { hipEvent_t ev; uint64_t id; };
+  std::deque<Step> inflight;
+  std::vector<hipEvent_t> spare_events;
+  uint64_t step_id = 0, done_step = 0;
   std::unordered_map<uint64_t, ServeResult> results;
   std::unordered_set<uint64_t> live;
   uint64_t next_ticket = 1;
@@ -532,24 +626,38 @@ struct ServeEngine {
   explicit ServeEngine(bcts_ctx* ctx) : c(ctx) {}
   ~ServeEngine() { release(); }
 
-  long long chunk_items() const { return (c->fused && c->prec != P_FP32) ? 8 * chunk : chunk; }
-  size_t fixed_bytes() const {
-    const long long ch = chunk_items() + kMaxA;
-    size_t ws = (c->fused && c->prec != P_FP32) ? fused_workspace_bytes(ch, c->prec)
-                                                 : qnet_workspace_bytes(ch, c->prec);
-    if (c->corr_fp32 && c->prec != P_FP32) ws = std::max(ws, qnet_workspace_bytes(chunk, P_FP32));
-    return ws + sizeof(ItemDesc) * ch + 8 * kAlign;
+  bool fused() const { return c->fused && c->prec != P_FP32; }
+  long long chunk_items() const { return fused() ? 8 * layer_chunk : layer_chunk; }
+  Settings current() const {
+    return Settings{c->prec, c->fused ? 1 : 0, c->fused_T, c->corr_fp32 ? 1 : 0, c->beam, chunk_items(),
+                    layer_chunk};
+  }
+  bool busy() const { return !queue.empty() || !active.empty(); }
+  size_t pool_capacity() const { return ready ? pool.capacity() : 0; }
+
+  // descriptors + workspace of the largest Q-network stage of any cohort
+  size_t shared_need() const {
+    const long long ch = chunk_items(), tail = layer_chunk;
+    size_t ws = fused() ? fused_workspace_bytes(ch, c->prec) : qnet_workspace_bytes(ch, c->prec);
+    ws = std::max(ws, qnet_workspace_bytes(tail, P_FP32));
+    return align_up(sizeof(ItemDesc) * (size_t)std::max(ch, tail)) + align_up(ws);
   }
 
   void release() {
-    for (auto& sl : slots) {
-      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-      if (sl.arena) (void)hipFree(sl.arena);
-      if (sl.pinned) (void)hipHostFree(sl.pinned);
-      if (sl.done) (void)hipEventDestroy(sl.done);
-      if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    }
-    slots.clear();
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& st : inflight) (void)hipEventDestroy(st.ev);
+    inflight.clear();
+    for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);
+    spare_events.clear();
+    active.clear();
+    if (dev) (void)hipFree(dev);
+    if (pinned) (void)hipHostFree(pinned);
+    if (stream) (void)hipStreamDestroy(stream);
+    dev = nullptr;
+    pinned = nullptr;
+    stream = nullptr;
+    dev_bytes = shared_bytes = 0;
+    ready = false;
   }
 
   void drop_all() {
@@ -559,118 +667,205 @@ struct ServeEngine {
     live.clear();
   }
 
+  // Allocate the pools for the context's current settings; an idle engine
+  // whose settings changed (precision, fusion, chunking, beam) is rebuilt.
   bcts_status init() {
-    if (!slots.empty()) return BCTS_OK;
+    const Settings now = current();
+    if (ready && now == cfg) return BCTS_OK;
+    if (ready && busy()) return fail(c, BCTS_E_STATE, "serving settings changed while requests are in flight");
+    release();
+    cfg = now;
     const size_t used = c->wbytes + c->arena_bytes;
     const size_t avail = c->budget > used ? c->budget - used : 0;
-    slot_cap = avail / (size_t)max_inflight;
-    if (slot_cap <= fixed_bytes())
-      return fail(c, BCTS_E_NOMEM, "serving budget too small (%zu bytes per slot)", slot_cap);
-    slots.resize(max_inflight);
-    for (auto& sl : slots) {
-      HIPCHECK(c, hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
-      HIPCHECK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    shared_bytes = shared_need();
+    if (avail <= shared_bytes + kAlign)
+      return fail(c, BCTS_E_NOMEM, "serving needs %zu bytes of workspace; the budget leaves %zu", shared_bytes, avail);
+    dev_bytes = std::min(avail, shared_bytes + kPoolCap) / kAlign * kAlign;
+    HIPCHECK(c, hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    hipError_t e = hipMalloc((void**)&dev, dev_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      dev = nullptr;
+      return fail(c, BCTS_E_NOMEM, "hipMalloc(%zu) for the serving pool failed: %s", dev_bytes, hipGetErrorString(e));
     }
+    HIPCHECK(c, hipHostMalloc((void**)&pinned, kPinnedBytes, hipHostMallocDefault));
+    pool.reset(dev_bytes - shared_bytes);
+    pin_pool.reset(kPinnedBytes);
+    ready = true;
     return BCTS_OK;
   }
 
+  hipEvent_t take_event() {
+    if (!spare_events.empty()) {
+      hipEvent_t e = spare_events.back();
+      spare_events.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+
+  // Finished steps, then the cohorts whose last stage they held.
   bcts_status retire() {
-    for (auto& sl : slots) {
-      if (!sl.busy) continue;
-      hipError_t e = hipEventQuery(sl.done);
-      if (e == hipErrorNotReady) continue;
-      if (e != hipSuccess) return fail(c, BCTS_E_HIP, "serving batch failed: %s", hipGetErrorString(e));
-      const double t = now_s();
-      const int32_t* act = reinterpret_cast<const int32_t*>(sl.pinned + sl.h_act);
-      const float* q = reinterpret_cast<const float*>(sl.pinned + sl.h_q);
-      for (size_t i = 0; i < sl.tickets.size(); ++i) {
+    while (!inflight.empty()) {
+      const hipError_t e = hipEventQuery(inflight.front().ev);
+      if (e == hipErrorNotReady) break;
+      if (e != hipSuccess) return fail(c, BCTS_E_HIP, "serving step failed: %s", hipGetErrorString(e));
+      done_step = inflight.front().id;
+      spare_events.push_back(inflight.front().ev);
+      inflight.pop_front();
+    }
+    const double t = now_s();
+    for (auto it = active.begin(); it != active.end();) {
+      Cohort& k = *it;
+      if (k.next < k.n_stages || k.last_step > done_step) { ++it; continue; }
+      const int32_t* act = reinterpret_cast<const int32_t*>(pinned + k.pin_off + k.h_act);
+      const float* q = reinterpret_cast<const float*>(pinned + k.pin_off + k.h_q);
+      for (size_t i = 0; i < k.tickets.size(); ++i) {
         ServeResult r;
         r.action = act[i];
-        r.A = sl.A[i];
+        r.A = k.A[i];
         for (int a = 0; a < kMaxA; ++a) r.q[a] = q[i * kMaxA + a];
         r.t_done = t;
-        if (live.count(sl.tickets[i])) results[sl.tickets[i]] = r;
+        if (live.count(k.tickets[i])) results[k.tickets[i]] = r;
       }
-      sl.busy = false;
+      pool.release(k.dev_off, k.p.search_bytes());
+      pin_pool.release(k.pin_off, k.pin_bytes);
+      ++cohorts_done;
+      requests_done += k.tickets.size();
+      it = active.erase(it);
     }
     return BCTS_OK;
   }
 
-  bcts_status launch(ServeSlot& sl) {
-    // FIFO prefix sharing (gamma, correction) within the slot's memory
-    const size_t cap = slot_cap - fixed_bytes();
+  // Admit the longest FIFO prefix of compatible requests that fits a
+  // cohort; returns false when the front request cannot be admitted now.
+  bool admit_one() {
+    if (queue.empty()) return false;
     const ServeReq& f = queue.front();
-    size_t sum = 0;
     int n = 0;
+    long long leaves = 0;
     for (const auto& r : queue) {
+      long long lv = 1;
+      for (int k = 0; k < r.d; ++k) lv *= r.A;
       if (n >= max_batch || r.gamma != f.gamma || r.corr.enabled != f.corr.enabled ||
-          r.corr.scale != f.corr.scale || r.corr.mode != f.corr.mode || sum + r.bytes > cap)
+          r.corr.scale != f.corr.scale || r.corr.mode != f.corr.mode || (n > 0 && leaves + lv > kCohortLeaves))
         break;
-      sum += r.bytes;
+      leaves += lv;
       ++n;
     }
-    if (n == 0) return BCTS_OK;
     std::vector<int32_t> dep(n), Av(n);
     for (int i = 0; i < n; ++i) { dep[i] = queue[i].d; Av[i] = queue[i].A; }
-    Plan p;
-    const bool fz = c->fused && c->prec != P_FP32;
-    make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam,
-              c->corr_fp32, chunk);
-    while (p.total > slot_cap && n > 1) {   // alignment slack: shrink the batch
-      --n;
-      make_plan(p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fz, c->beam,
-                c->corr_fp32, chunk);
+    for (;;) {
+      Cohort k;
+      make_plan(k.p, n, dep.data(), Av.data(), f.gamma, f.corr, kMaxA, chunk_items(), c->prec, true, fused(),
+                c->beam, c->corr_fp32, layer_chunk);
+      k.h_pos = align_up(k.p.table_bytes);
+      k.h_stack = k.h_pos + align_up(sizeof(int32_t) * n * kSprites * 2);
+      k.h_act = k.h_stack + align_up((size_t)n * 4 * kFrameBytes);
+      k.h_q = k.h_act + align_up(sizeof(int32_t) * n);
+      k.pin_bytes = k.h_q + align_up(sizeof(float) * (size_t)n * kMaxA);
+      bool ok = pool.alloc(k.p.search_bytes(), &k.dev_off);
+      if (ok && !pin_pool.alloc(k.pin_bytes, &k.pin_off)) {
+        pool.release(k.dev_off, k.p.search_bytes());
+        ok = false;
+      }
+      if (!ok) {
+        if (n == 1) return false;     // wait for memory (arrival order is kept)
+        n = (n + 1) / 2;              // a smaller prefix may fit now
+        continue;
+      }
+      // stage the tables and inputs in the cohort's pinned range
+      char* h = pinned + k.pin_off;
+      const Plan& p = k.p;
+      std::memcpy(h + p.o_roots, p.roots.data(), sizeof(RootInfo) * p.n);
+      std::memcpy(h + p.o_segs, p.segs.data(), sizeof(Seg) * p.segs.size());
+      std::memcpy(h + p.o_groups, p.groups.data(), sizeof(FusedGroup) * p.groups.size());
+      for (int lv = 1; lv <= p.maxd; ++lv) {
+        std::memcpy(h + p.o_lroot[lv], p.lvl_root[lv].data(), sizeof(int) * p.lvl_root[lv].size());
+        std::memcpy(h + p.o_lstart[lv], p.lvl_start[lv].data(), sizeof(long long) * p.lvl_start[lv].size());
+      }
+      int32_t* hp = reinterpret_cast<int32_t*>(h + k.h_pos);
+      uint8_t* hs = reinterpret_cast<uint8_t*>(h + k.h_stack);
+      k.tickets.resize(n);
+      k.A.resize(n);
+      for (int i = 0; i < n; ++i) {
+        const ServeReq& r = queue[i];
+        std::memcpy(hp + i * kSprites * 2, r.pos, sizeof r.pos);
+        std::memcpy(hs + (size_t)i * 4 * kFrameBytes, r.stack.data(), (size_t)4 * kFrameBytes);
+        k.tickets[i] = r.ticket;
+        k.A[i] = r.A;
+      }
+      k.gamma = f.gamma;
+      k.corr = f.corr;
+      k.n_stages = p.maxd + (int)p.chunks.size() + (p.tail_chunks.empty() ? 0 : 1) + 1;
+      long long work = p.n_items;
+      for (int lv = 1; lv <= p.maxd; ++lv) work += p.lvl_count[lv];
+      k.light = work <= kLightWork;
+      for (int i = 0; i < n; ++i) queue.pop_front();
+      active.push_back(std::move(k));
+      return true;
     }
-    if (p.total > slot_cap) return fail(c, BCTS_E_NOMEM, "request does not fit a serving slot");
-    if (sl.arena_bytes < slot_cap) {
-      if (sl.arena) HIPCHECK(c, hipFree(sl.arena));
-      sl.arena = nullptr;
-      sl.arena_bytes = 0;
-      HIPCHECK(c, hipMalloc((void**)&sl.arena, slot_cap));
-      sl.arena_bytes = slot_cap;
+  }
+
+  // Stage `i` of cohort k on the engine stream (stage 0 also uploads).
+  bcts_status enqueue_stage(Cohort& k, int i) {
+    const Plan& p = k.p;
+    char* A = dev + shared_bytes + k.dev_off;
+    char* h = pinned + k.pin_off;
+    ItemDesc* desc = reinterpret_cast<ItemDesc*>(dev);
+    char* ws = dev + align_up(sizeof(ItemDesc) * (size_t)std::max(chunk_items(), layer_chunk));
+    const int32_t* d_pos = reinterpret_cast<const int32_t*>(A + p.o_root_pos);
+    const uint8_t* d_stacks = reinterpret_cast<const uint8_t*>(A + p.o_root_stack);
+    const int n = p.n;
+    if (i == 0) {
+      HIPCHECK(c, hipMemcpyAsync(A, h, p.table_bytes, hipMemcpyHostToDevice, stream));
+      HIPCHECK(c, hipMemcpyAsync(A + p.o_root_pos, h + k.h_pos, sizeof(int32_t) * n * kSprites * 2,
+                                 hipMemcpyHostToDevice, stream));
+      HIPCHECK(c, hipMemcpyAsync(A + p.o_root_stack, h + k.h_stack, (size_t)n * 4 * kFrameBytes,
+                                 hipMemcpyHostToDevice, stream));
     }
-    const size_t in_pos = align_up(p.table_bytes), in_stack = in_pos + align_up(sizeof(int32_t) * n * 16);
-    sl.h_act = in_stack + align_up((size_t)n * 4 * kFrameBytes);
-    sl.h_q = sl.h_act + align_up(sizeof(int32_t) * n);
-    const size_t need = sl.h_q + align_up(sizeof(float) * (size_t)n * kMaxA);
-    if (sl.pinned_bytes < need) {
-      if (sl.pinned) HIPCHECK(c, hipHostFree(sl.pinned));
-      sl.pinned = nullptr;
-      sl.pinned_bytes = 0;
-      const size_t nb = std::max(need * 2, (size_t)1 << 20);
-      HIPCHECK(c, hipHostMalloc((void**)&sl.pinned, nb, hipHostMallocDefault));
-      sl.pinned_bytes = nb;
-    }
-    bcts_status st = upload_tables_at(c, p, sl.arena, sl.pinned, sl.stream);
+    const int nl = p.maxd, nc = (int)p.chunks.size(), nt = p.tail_chunks.empty() ? 0 : 1;
+    if (i < nl) return enqueue_level(c, p, A, i + 1, d_pos, k.gamma, stream);
+    const FrameBases fb = frame_bases(p, A, d_stacks);
+    if (i < nl + nc) return enqueue_qnet_chunk(c, p, A, desc, ws, fb, i - nl, stream, nullptr);
+    if (i < nl + nc + nt) return enqueue_tail(c, p, A, desc, ws, fb, stream);
+    int32_t* d_act = reinterpret_cast<int32_t*>(A + p.o_act);
+    float* d_q = reinterpret_cast<float*>(A + p.o_q);
+    bcts_status st = enqueue_backup(c, p, A, k.gamma, k.corr.enabled ? k.corr.scale : 0.f, d_act, d_q, stream);
     if (st != BCTS_OK) return st;
-    int32_t* hp = reinterpret_cast<int32_t*>(sl.pinned + in_pos);
-    uint8_t* hs = reinterpret_cast<uint8_t*>(sl.pinned + in_stack);
-    sl.tickets.resize(n);
-    sl.A.resize(n);
-    for (int i = 0; i < n; ++i) {
-      const ServeReq& r = queue[i];
-      std::memcpy(hp + i * 16, r.pos, sizeof r.pos);
-      std::memcpy(hs + (size_t)i * 4 * kFrameBytes, r.stack.data(), (size_t)4 * kFrameBytes);
-      sl.tickets[i] = r.ticket;
-      sl.A[i] = r.A;
+    HIPCHECK(c, hipMemcpyAsync(h + k.h_act, d_act, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream));
+    HIPCHECK(c, hipMemcpyAsync(h + k.h_q, d_q, sizeof(float) * (size_t)n * kMaxA, hipMemcpyDeviceToHost, stream));
+    return BCTS_OK;
+  }
+
+  // One step: admissions, then one stage of every cohort (all of a light
+  // one).  Returns whether anything was enqueued.
+  bcts_status step(bool* did) {
+    *did = false;
+    while (admit_one()) {
     }
-    HIPCHECK(c, hipMemcpyAsync(sl.arena + p.o_root_pos, hp, sizeof(int32_t) * n * 16, hipMemcpyHostToDevice,
-                               sl.stream));
-    HIPCHECK(c, hipMemcpyAsync(sl.arena + p.o_root_stack, hs, (size_t)n * 4 * kFrameBytes,
-                               hipMemcpyHostToDevice, sl.stream));
-    int32_t* d_act = reinterpret_cast<int32_t*>(sl.arena + p.o_act);
-    float* d_q = reinterpret_cast<float*>(sl.arena + p.o_q);
-    st = enqueue_search_at(c, p, sl.arena, reinterpret_cast<const int32_t*>(sl.arena + p.o_root_pos),
-                           reinterpret_cast<const uint8_t*>(sl.arena + p.o_root_stack), f.gamma,
-                           f.corr.enabled ? f.corr.scale : 0.f, d_act, d_q, sl.stream, false);
-    if (st != BCTS_OK) return st;
-    HIPCHECK(c, hipMemcpyAsync(sl.pinned + sl.h_act, d_act, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
-                               sl.stream));
-    HIPCHECK(c, hipMemcpyAsync(sl.pinned + sl.h_q, d_q, sizeof(float) * (size_t)n * kMaxA,
-                               hipMemcpyDeviceToHost, sl.stream));
-    HIPCHECK(c, hipEventRecord(sl.done, sl.stream));
-    sl.busy = true;
-    for (int i = 0; i < n; ++i) queue.pop_front();
+    const uint64_t id = step_id + 1;
+    bool any = false;
+    for (Cohort& k : active) {
+      if (k.next >= k.n_stages) continue;
+      const int upto = k.light ? k.n_stages : k.next + 1;
+      for (; k.next < upto; ++k.next) {
+        const bcts_status st = enqueue_stage(k, k.next);
+        if (st != BCTS_OK) return st;
+      }
+      if (k.next == k.n_stages) k.last_step = id;
+      any = true;
+    }
+    if (!any) return BCTS_OK;
+    HIPCHECK(c, hipGetLastError());
+    hipEvent_t ev = take_event();
+    if (!ev) return fail(c, BCTS_E_HIP, "hipEventCreate failed");
+    HIPCHECK(c, hipEventRecord(ev, stream));
+    inflight.push_back(Step{ev, id});
+    step_id = id;
+    *did = true;
     return BCTS_OK;
   }
 
@@ -678,30 +873,28 @@ struct ServeEngine {
     bcts_status st = init();
     if (st != BCTS_OK) return st;
     if ((st = retire()) != BCTS_OK) return st;
-    for (auto& sl : slots) {
-      if (queue.empty()) break;
-      if (sl.busy) continue;
-      if ((st = launch(sl)) != BCTS_OK) return st;
+    while ((int)inflight.size() < max_steps) {
+      bool did = false;
+      if ((st = step(&did)) != BCTS_OK) return st;
+      if (!did) break;
     }
     if (pending) {
-      int busy = 0;
-      for (auto& sl : slots) busy += sl.busy ? (int)sl.tickets.size() : 0;
-      *pending = (int)queue.size() + busy;
+      int n = (int)queue.size();
+      for (const auto& k : active) n += (int)k.tickets.size();
+      *pending = n;
     }
     return BCTS_OK;
   }
 };
 
 // Serving work that reads the context's model, tables and settings: queued
-// requests and batches in flight (finished results waiting for bcts_poll do
+// requests and admitted cohorts (finished results waiting for bcts_poll do
 // not count).  The calls that change that state refuse while it exists.
 static bcts_status refuse_if_serving(bcts_ctx* c, const char* what) {
   if (!c->serve) return BCTS_OK;
   bcts_status st = c->serve->retire();
   if (st != BCTS_OK) return st;
-  bool busy = !c->serve->queue.empty();
-  for (const auto& sl : c->serve->slots) busy = busy || sl.busy;
-  if (busy) return fail(c, BCTS_E_STATE, "%s: serving requests are queued or in flight", what);
+  if (c->serve->busy()) return fail(c, BCTS_E_STATE, "%s: serving requests are queued or in flight", what);
   return BCTS_OK;
 }
 
@@ -1296,12 +1489,13 @@ bcts_status bcts_serve_config(bcts_ctx* c, int32_t max_batch, int32_t max_inflig
   if (st != BCTS_OK) return st;
   if (max_batch < 1 || max_inflight < 1 || max_inflight > 8)
     return fail(c, BCTS_E_INVAL, "max_batch >= 1 and 1 <= max_inflight <= 8");
-  if (c->serve && (!c->serve->queue.empty() || !c->serve->live.empty()))
+  if (c->serve && (c->serve->busy() || !c->serve->live.empty()))
     return fail(c, BCTS_E_STATE, "serving is active");
+  HIPCHECK(c, hipSetDevice(c->device));
   delete c->serve;
   c->serve = new ServeEngine(c);
   c->serve->max_batch = max_batch;
-  c->serve->max_inflight = max_inflight;
+  c->serve->max_steps = max_inflight;
   return BCTS_OK;
 }
 
@@ -1317,11 +1511,11 @@ bcts_status bcts_submit(bcts_ctx* c, const int32_t* pos, const uint8_t* stack, i
   if (!c->serve) c->serve = new ServeEngine(c);
   ServeEngine& e = *c->serve;
   if ((st = e.init()) != BCTS_OK) return st;
+  const size_t need = request_bytes(depth, A);
+  if (need > e.pool_capacity())
+    return fail(c, BCTS_E_NOMEM, "request (depth %d, A %d) needs %zu bytes; the serving pool holds %zu", depth, A,
+                need, e.pool_capacity());
   ServeReq r;
-  r.bytes = request_bytes(depth, A);
-  if (r.bytes > e.slot_cap - e.fixed_bytes())
-    return fail(c, BCTS_E_NOMEM, "request (depth %d, A %d) needs %zu bytes; a serving slot holds %zu", depth, A,
-                r.bytes, e.slot_cap - e.fixed_bytes());
   r.ticket = e.next_ticket++;
   r.A = A;
   r.d = depth;
@@ -1333,6 +1527,33 @@ bcts_status bcts_submit(bcts_ctx* c, const int32_t* pos, const uint8_t* stack, i
   *ticket = r.ticket;
   e.queue.push_back(std::move(r));
   return e.progress(nullptr);
+}
+
+bcts_status bcts_serve_stats(bcts_ctx* c, int64_t* out8) {
+  if (!c || !out8) return BCTS_E_INVAL;
+  for (int i = 0; i < 8; ++i) out8[i] = 0;
+  const ServeEngine* e = c->serve;
+  if (!e) return BCTS_OK;
+  int64_t admitted = 0, staged = 0;
+  for (const auto& k : e->active) {
+    admitted += (int64_t)k.tickets.size();
+    staged += k.next < k.n_stages ? 1 : 0;
+  }
+  out8[0] = (int64_t)e->queue.size();
+  out8[1] = admitted;
+  out8[2] = (int64_t)e->active.size();
+  out8[3] = staged;
+  out8[4] = (int64_t)e->inflight.size();
+  out8[5] = (int64_t)(e->ready ? e->pool.in_use() : 0);
+  out8[6] = (int64_t)e->pool_capacity();
+  out8[7] = (int64_t)e->cohorts_done;
+  return BCTS_OK;
+}
+
+bcts_status bcts_debug_fail_launches(bcts_ctx* c, int32_t count) {
+  if (!c || count < 0) return BCTS_E_INVAL;
+  c->inject_fail = count;
+  return BCTS_OK;
 }
 
 bcts_status bcts_progress(bcts_ctx* c, int32_t* pending) {
