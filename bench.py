@@ -325,7 +325,7 @@ def run_mlp(args):
     stream = torch.cuda.Stream()
     corr = bcts.correction(True, C)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    rows, batched = [], {}
+    rows, batched, crossover = [], {}, []
     cpu_rows = []
     for A, dmax in ((2, 14), (10, 6)):
         ctx = bcts.Context(0)
@@ -358,9 +358,29 @@ def run_mlp(args):
             ms = e0.elapsed_time(e1) / args.steps
             batched[A] = {"roots": 64, "depth": d, "leaves": 64 * A ** d, "ms_per_step": ms,
                           "leaf_evals_per_s": 64 * A ** d / (ms * 1e-3)}
+        # CPU-to-GPU cross-over (Sec. 4.1): host-buffer searches of one root
+        # (the state starts on the host, the result returns to it), levels
+        # 1..k on the CPU and the rest on the GPU, against depth
+        st_h = W.mlp_states(MLP_SEED, 64)
+        for d in range(1, min(dmax, 8 if A == 2 else 5) + 1):
+            row = {"A": A, "depth": d}
+            for k in range(0, min(d - 1, 3) + 1):
+                ctx.set_tuning(bcts.TUNE_MLP_CROSSOVER, k)
+                for i in range(3):
+                    ctx.mlp_search(st_h[i:i + 1], d, A, GAMMA, corr)
+                reps = 40 if A ** d < 10 ** 4 else 10
+                t0 = time.perf_counter()
+                for i in range(reps):
+                    ctx.mlp_search(st_h[i % 64:i % 64 + 1], d, A, GAMMA, corr)
+                row[f"host_levels_{k}_ms"] = (time.perf_counter() - t0) / reps * 1e3
+            ctx.set_tuning(bcts.TUNE_MLP_CROSSOVER, 0)
+            times = {k: v for k, v in row.items() if k.startswith("host_levels_")}
+            row["best_crossover_depth"] = int(min(times, key=times.get).split("_")[2])
+            crossover.append(row)
         ctx.close()
         print(f"# mlp A={A}: {[(r['depth'], round(r['gpu_ms_per_search'], 4)) for r in rows if r['A'] == A]}",
               file=sys.stderr, flush=True)
+        print(f"# mlp A={A} cross-over: {[r for r in crossover if r['A'] == A]}", file=sys.stderr, flush=True)
     if args.cpu_sample > 0:
         for A, dmax in ((2, 10), (10, 4)):
             for d in range(1, dmax + 1):
@@ -375,6 +395,10 @@ def run_mlp(args):
         "config": {"workload": f"64 root states, A=10, depth {head['depth']}, gamma 0.99, BCTS c=1.0; per-search "
                                "times: one root per search, A in {2, 10}, depth 1..14 / 1..6"},
         "batched": batched, "per_search": rows,
+        "crossover": {"rows": crossover,
+                      "what": "ms per host-buffer search of one root (state in, action and root vector out, PCIe "
+                              "included) with levels 1..k expanded on the host CPU and the rest on the GPU; "
+                              "best_crossover_depth = the fastest k"},
         "cpu_baseline": {"kind": "oracle", "cores": 1, "rows": cpu_rows,
                          "sample": "FP64 depth-first search of one root on one host core, averaged over up to "
                                    "16 roots within 2 s per depth"} if cpu_rows else None,

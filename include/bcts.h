@@ -213,13 +213,22 @@ bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_
  *                          depth-1 nodes are the leaves; their A FP32
  *                          evaluations are then extra work.  0 = every
  *                          evaluation at the search precision (at depth 1
- *                          the Bellman errors read the leaves' values). */
+ *                          the Bellman errors read the leaves' values).
+ *   BCTS_TUNE_MLP_CROSSOVER  forward-model world, host-buffer searches
+ *                          (bcts_mlp_search): the CPU-to-GPU cross-over of
+ *                          Sec. 4.1 -- levels 1..k of the tree are expanded
+ *                          on the host CPU, the rest (and every leaf) on
+ *                          the GPU, k = min(value, depth - 1); 0 (default)
+ *                          = the whole search on the GPU.  The host levels
+ *                          do the device kernel's FP32 arithmetic in the
+ *                          same order, so results are the same bits.       */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
   BCTS_TUNE_FUSED_CHUNK = 2,
   BCTS_TUNE_LAYER_CHUNK = 3,
-  BCTS_TUNE_CORR_FP32 = 4
+  BCTS_TUNE_CORR_FP32 = 4,
+  BCTS_TUNE_MLP_CROSSOVER = 5
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);

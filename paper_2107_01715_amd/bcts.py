@@ -44,7 +44,7 @@ EXPORTS = (
     "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc", "bcts_serve_stats",
     "bcts_debug_fail_launches",
 )
-TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32 = 0, 1, 2, 3, 4
+TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32, TUNE_MLP_CROSSOVER = 0, 1, 2, 3, 4, 5
 
 
 class EnvParamsC(ctypes.Structure):

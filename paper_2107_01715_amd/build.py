@@ -13,9 +13,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbcts.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "plan.cpp", "expand.hip", "qnet.hip", "qnet_fused.hip", "fc.hip", "backup.hip", "mlp.hip"]
+SOURCES = ["api.hip", "plan.cpp", "mlp_host.cpp", "expand.hip", "qnet.hip", "qnet_fused.hip", "fc.hip", "backup.hip",
+           "mlp.hip"]
 ARCH = os.environ.get("BCTS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
 
 # packed-FP32 instructions stay disabled (the compiler would otherwise form
 # v_pk_* FP32 ops from plain float code).
@@ -24,9 +26,16 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-
          "-I", os.path.join(HERE, "..", "include")]
 
 
+# host-only sources (no HIP): the C++ compiler, FP contraction off
+HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-ffp-contract=off", "-fno-math-errno", "-I", os.path.join(HERE, "..", "include")]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [CXX, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

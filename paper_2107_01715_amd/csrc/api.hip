@@ -27,8 +27,11 @@
 #include "../../include/bcts.h"
 #include "bcts_internal.h"
 #include "plan.h"
+#include "mlp_host.h"
 
 using namespace bcts;
+
+constexpr int kMlpMaxD = 16;            // deepest forward-model search
 
 namespace {
 
@@ -101,10 +104,13 @@ struct bcts_ctx {
   struct ServeEngine* serve = nullptr;
   // launches still to fail on purpose (bcts_debug_fail_launches)
   int inject_fail = 0;
-  // learned forward-model world
+  // learned forward-model world (device weights, and a host copy for the
+  // host levels of a search that starts on the CPU)
   void* mlp_mem = nullptr;
   MlpDev mlp{};
   bool mlp_set = false;
+  MlpHost mlp_h{};
+  int mlp_crossover = 0;               // levels a host-buffer search expands on the CPU
 };
 
 namespace {
@@ -1605,6 +1611,11 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
       if (value < 1 || value > (1LL << 22)) return fail(c, BCTS_E_INVAL, "layer chunk out of range");
       c->chunk_items = value;
       return BCTS_OK;
+    case BCTS_TUNE_MLP_CROSSOVER:
+      if (value < 0 || value > kMlpMaxD) return fail(c, BCTS_E_INVAL, "cross-over depth %lld outside [0,%d]",
+                                                     (long long)value, kMlpMaxD);
+      c->mlp_crossover = (int)value;
+      return BCTS_OK;
     case BCTS_TUNE_CORR_FP32:
       c->corr_fp32 = value != 0;
       return BCTS_OK;
@@ -1621,6 +1632,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_FUSED_CHUNK: *value = c->fused_chunk_items; return BCTS_OK;
     case BCTS_TUNE_LAYER_CHUNK: *value = c->chunk_items; return BCTS_OK;
     case BCTS_TUNE_CORR_FP32: *value = c->corr_fp32 ? 1 : 0; return BCTS_OK;
+    case BCTS_TUNE_MLP_CROSSOVER: *value = c->mlp_crossover; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }
@@ -1726,7 +1738,6 @@ bcts_status bcts_get_timing(bcts_ctx* c, double* out24) {
 // ---- learned forward-model world (Sec. 4.1) --------------------------------
 
 namespace {
-constexpr int kMlpMaxD = 16;
 
 size_t mlp_numel(int A) {
   return (size_t)100 * (100 + A) + 100 + 100 * 100 + 100 + 100 * 100 + 100 + 101 * 100 + 101 + (size_t)A * 100 + A;
@@ -1779,7 +1790,7 @@ bcts_status mlp_validate(bcts_ctx* c, int n, int d, float gamma, const bcts_corr
 // return + gamma^d max Q, reduced per (root, root action); then the root
 // values and the correction.
 void mlp_enqueue(bcts_ctx* c, const MlpPlan& p, int n, int d, const float* states, float gamma,
-                 const bcts_correction& corr, int32_t* act, float* q, hipStream_t s) {
+                 const bcts_correction& corr, int32_t* act, float* q, hipStream_t s, int k0 = 0) {
   const int A = c->mlp.A;
   char* base = c->arena;
   auto F = [&](size_t off) { return reinterpret_cast<float*>(base + off); };
@@ -1788,6 +1799,7 @@ void mlp_enqueue(bcts_ctx* c, const MlpPlan& p, int n, int d, const float* state
   long long cnt = n;
   for (int k = 1; k <= d; ++k) {
     cnt *= A;
+    if (k <= k0) continue;             // expanded on the host
     const float* ps = k == 1 ? states : F(p.states[k - 1]);
     const float* pret = k == 1 ? nullptr : F(p.ret[k - 1]);
     float* os = k < d ? F(p.states[k]) : nullptr;
@@ -1836,22 +1848,25 @@ bcts_status bcts_set_mlp(bcts_ctx* c, int32_t A, const float* blob, size_t n_flo
   }
   HIPCHECK(c, hipMalloc(&c->mlp_mem, sizeof(float) * h.size()));
   HIPCHECK(c, hipMemcpy(c->mlp_mem, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
-  const float* d0 = static_cast<const float*>(c->mlp_mem);
-  size_t o = 0;
-  auto next = [&](size_t k) { const float* p = d0 + o; o += k; return p; };
+  mlp_host_prepare(c->mlp_h, A, h.data());
+  auto carve = [&](const float* d0, auto& m) {
+    size_t o = 0;
+    auto next = [&](size_t k) { const float* p = d0 + o; o += k; return p; };
+    m.A = A;
+    m.w1s = next(100 * 100);
+    m.w1a = next((size_t)A * 100);
+    m.b1 = next(100);
+    m.w2 = next(100 * 100);
+    m.b2 = next(100);
+    m.w3 = next(100 * 100);
+    m.b3 = next(100);
+    m.wo = next(101 * 100);
+    m.bo = next(101);
+    m.wq = next((size_t)A * 100);
+    m.bq = next(A);
+  };
   MlpDev m;
-  m.A = A;
-  m.w1s = next(100 * 100);
-  m.w1a = next((size_t)A * 100);
-  m.b1 = next(100);
-  m.w2 = next(100 * 100);
-  m.b2 = next(100);
-  m.w3 = next(100 * 100);
-  m.b3 = next(100);
-  m.wo = next(101 * 100);
-  m.bo = next(101);
-  m.wq = next((size_t)A * 100);
-  m.bq = next(A);
+  carve(static_cast<const float*>(c->mlp_mem), m);
   c->mlp = m;
   c->mlp_set = true;
   return BCTS_OK;
@@ -1890,10 +1905,48 @@ bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, i
   const int A = c->mlp.A;
   HIPCHECK(c, hipMemcpyAsync(c->arena + p.in_states, states, sizeof(float) * 100 * (size_t)n_roots,
                              hipMemcpyHostToDevice, c->stream));
+  // CPU-to-GPU cross-over: levels 1..k0 on the host (never the leaves, which
+  // the Q-head scores on the device), their last level's states and returns
+  // -- and level 1's returns and head values, which the correction reads --
+  // then go to the device, which continues at level k0 + 1
+  const int k0 = std::min(c->mlp_crossover, depth - 1);
+  if (k0 > 0) {
+    const bool corr_on = corr.enabled && depth >= 1;
+    long long cnt_k0 = n_roots;
+    for (int k = 1; k <= k0; ++k) cnt_k0 *= A;
+    const size_t s_bytes = sizeof(float) * 100 * (size_t)cnt_k0, r_bytes = sizeof(float) * (size_t)cnt_k0;
+    const size_t l1 = (size_t)n_roots * A;
+    const size_t need = align_up(s_bytes) + align_up(r_bytes) + 2 * align_up(sizeof(float) * l1);
+    if ((st = ensure_pinned(c, need)) != BCTS_OK) return st;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));      // the pinned buffer is free
+    float* hs = reinterpret_cast<float*>(c->pinned);
+    float* hr = reinterpret_cast<float*>(c->pinned + align_up(s_bytes));
+    float* hr1 = reinterpret_cast<float*>(c->pinned + align_up(s_bytes) + align_up(r_bytes));
+    float* hv1 = hr1 + align_up(sizeof(float) * l1) / sizeof(float);
+    std::vector<float> ps(states, states + (size_t)n_roots * 100), pr, ns, nr;
+    long long cnt = n_roots;
+    for (int k = 1; k <= k0; ++k) {
+      cnt *= A;
+      const bool last = k == k0;
+      ns.resize(last ? 0 : (size_t)cnt * 100);
+      nr.resize(last ? 0 : (size_t)cnt);
+      mlp_host_level(c->mlp_h, cnt, ps.data(), k == 1 ? nullptr : pr.data(),
+                     (float)std::pow((double)gamma, (double)(k - 1)), last ? hs : ns.data(),
+                     last ? hr : nr.data(), (k == 1 && corr_on) ? hv1 : nullptr);
+      if (k == 1) std::memcpy(hr1, last ? hr : nr.data(), sizeof(float) * l1);
+      ps.swap(ns);
+      pr.swap(nr);
+    }
+    auto D = [&](size_t off) { return c->arena + off; };
+    HIPCHECK(c, hipMemcpyAsync(D(p.states[k0]), hs, s_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(D(p.ret[k0]), hr, r_bytes, hipMemcpyHostToDevice, c->stream));
+    if (k0 > 1) HIPCHECK(c, hipMemcpyAsync(D(p.ret[1]), hr1, sizeof(float) * l1, hipMemcpyHostToDevice, c->stream));
+    if (corr_on) HIPCHECK(c, hipMemcpyAsync(D(p.v1), hv1, sizeof(float) * l1, hipMemcpyHostToDevice, c->stream));
+  }
   int32_t* d_act = reinterpret_cast<int32_t*>(c->arena + p.out_act);
   float* d_q = reinterpret_cast<float*>(c->arena + p.out_q);
   mlp_enqueue(c, p, n_roots, depth, reinterpret_cast<const float*>(c->arena + p.in_states), gamma, corr, d_act, d_q,
-              c->stream);
+              c->stream, k0);
   HIPCHECK(c, hipGetLastError());
   HIPCHECK(c, hipMemcpyAsync(out_action, d_act, sizeof(int32_t) * (size_t)n_roots, hipMemcpyDeviceToHost, c->stream));
   HIPCHECK(c, hipMemcpyAsync(out_q, d_q, sizeof(float) * (size_t)n_roots * A, hipMemcpyDeviceToHost, c->stream));

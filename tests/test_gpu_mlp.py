@@ -127,3 +127,41 @@ def test_argument_errors(lib):
         ctx.mlp_search(bad_states, 2, 2, GAMMA, lib.correction())
     assert e.value.status == lib.E_INVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("crossover", [1, 2, 3])
+def test_crossover_equals_gpu_search(lib, model, crossover):
+    """CPU-to-GPU cross-over (Sec. 4.1): the first `crossover` levels on the
+    host, the rest on the device.  The host levels do the device kernel's
+    FP32 arithmetic in the same order, so actions and root vectors are the
+    all-GPU search's bit for bit, for every depth it applies to (the leaves
+    always stay on the device), with and without the correction, in both
+    correction modes."""
+    ctx, A, w = model
+    n = 3
+    st = W.mlp_states(103, n)
+    for d in range(0, 6 if A == 2 else 5):
+        for corr in (lib.correction(True, 1.0), lib.correction(False, 0.0),
+                     lib.correction(True, 0.5, lib.CORR_EXACT_GEV)):
+            ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, 0)
+            a0, q0 = ctx.mlp_search(st, d, A, GAMMA, corr)
+            ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, crossover)
+            a1, q1 = ctx.mlp_search(st, d, A, GAMMA, corr)
+            ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, 0)
+            assert np.array_equal(a0, a1), (d, crossover)
+            assert np.array_equal(q0, q1), (d, crossover, np.abs(q0 - q1).max())
+    if A == 2:                                   # and against the oracle at the deepest case
+        ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, crossover)
+        act, q = ctx.mlp_search(st, 5, A, GAMMA, lib.correction(True, 1.0))
+        ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, 0)
+        for r in range(n):
+            ref = M.search(w, st[r].astype(np.float64), 5, A, GAMMA, correction=True, c=1.0)
+            check(q[r], int(act[r]), ref, f"A={A} d=5 crossover {crossover} root {r}")
+
+
+def test_crossover_argument(lib, model):
+    ctx, _, _ = model
+    with pytest.raises(lib.BctsError) as e:
+        ctx.set_tuning(lib.TUNE_MLP_CROSSOVER, 17)
+    assert e.value.status == lib.E_INVAL
+    assert ctx.get_tuning(lib.TUNE_MLP_CROSSOVER) == 0
