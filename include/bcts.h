@@ -350,6 +350,28 @@ bcts_status bcts_debug_expand(bcts_ctx* ctx, const int32_t* pos, const uint8_t* 
  * already enqueued runs to completion.                                     */
 bcts_status bcts_debug_fail_launches(bcts_ctx* ctx, int32_t count);
 
+/* Expand a batch of roots of mixed (depth, A) to their depths with the
+ * context's beam (Alg. 1's loop body for every root at once, the pruned
+ * search's keep lists included) and copy every node out as the search's
+ * own tables lay it out.  Sizes first: with out_pos NULL only
+ *   level_nodes [7]     nodes of level k (index k = 1..6) over all roots,
+ *   keep_entries [7]    keep-list entries of level k over all roots,
+ *   root_levels [n][7][3]  per root and level: first node of the root in the
+ *                       level, its node count, its first keep-list entry
+ *                       (-1: the level is not cut for that root; entries
+ *                       a0 * beam .. hold root action a0's kept nodes as
+ *                       root-local indices, ascending)
+ * are filled.  Then, level after level (roots in order, each root's nodes
+ * in the index order of Alg. 1 among the children of its kept nodes):
+ * out_pos int32 [..][8][2], out_frames uint8 [..][84][84], out_reward int32
+ * [..], out_ret float [..] (the FP32 discounted return a beam ranks by),
+ * out_keep int32 [..] (all keep lists, level after level).  stacks is read
+ * only for validation of its presence (the expansion reads positions).    */
+bcts_status bcts_debug_expand_batch(bcts_ctx* ctx, int32_t n_roots, const int32_t* pos, const uint8_t* stacks,
+                                    const int32_t* depth, const int32_t* A, float gamma, int64_t* level_nodes,
+                                    int64_t* keep_entries, int64_t* root_levels, int32_t* out_pos,
+                                    uint8_t* out_frames, int32_t* out_reward, float* out_ret, int32_t* out_keep);
+
 /* Q-network on n host stacks at the current precision: out_q float [n][A]. */
 bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
                             float* out_q);

@@ -29,6 +29,7 @@ floor(i / A^(d-1)).
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -194,22 +195,80 @@ def node_at(world: World, pos, stack, acts):
     return p, s, rs
 
 
+# ---- the FP32 returns a pruned search ranks by --------------------------
+# Pruning decides which nodes survive by comparing discounted returns, so
+# both sides must take that decision on the same values.  The rule (stated
+# here and followed by the library): with g = the FP32 value of gamma,
+#   * the discount of a level-k reward is d_k = RN32(g^(k-1)), the FP32 value
+#     nearest the exact power (ties to even);
+#   * a level-k node's FP32 return is R_k = RN32(R_{k-1} + d_k * r_k) with
+#     R_0 = 0: the exact product and sum, rounded once (a fused
+#     multiply-add).
+# Both roundings are taken here on exact rationals.
+
+def round_f32(x: Fraction) -> float:
+    """The FP32 value nearest the exact rational x, ties to even (normal
+    range and zero; subnormal and overflowing values do not occur here)."""
+    if x == 0:
+        return 0.0
+    sign = -1 if x < 0 else 1
+    x = abs(x)
+    e = x.numerator.bit_length() - x.denominator.bit_length()      # 2^e <= x < 2^(e+2)
+    while Fraction(2) ** e > x:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= x:
+        e += 1
+    assert -126 <= e <= 127, e
+    scaled = x / Fraction(2) ** (e - 23)                       # in [2^23, 2^24)
+    m = scaled.numerator // scaled.denominator
+    rest = scaled - m
+    if rest > Fraction(1, 2) or (rest == Fraction(1, 2) and m % 2 == 1):
+        m += 1
+    return sign * float(Fraction(m) * Fraction(2) ** (e - 23))
+
+
 def level_discounts_f32(gamma: float, d: int) -> list:
-    """The FP32 discount of each level's reward as the library forms it: the
-    host multiplies the FP32 gamma into a double level by level and rounds
-    each power to FP32 (gamma^(k-1) for level k)."""
-    g, gf, out = 1.0, float(np.float32(gamma)), []
-    for _ in range(d):
-        out.append(float(np.float32(g)))
-        g *= gf
+    """[d_1, .., d_d] with d_k = RN32(g^(k-1)), g the FP32 value of gamma."""
+    g = Fraction(float(np.float32(gamma)))
+    return [round_f32(g ** (k - 1)) for k in range(1, d + 1)]
+
+
+def ret_step_f32(prev: float, dk: float, r: int) -> float:
+    """R_k = RN32(R_{k-1} + d_k r_k), one rounding of the exact value."""
+    return round_f32(Fraction(prev) + Fraction(dk) * r)
+
+
+def beam_levels(world: World, pos, stack, d: int, A: int, gamma: float, beam: int):
+    """The levels of the pruned search (rule: see search_beam).  Returns, per
+    level k = 1..d, (nodes, kept): nodes lists every expanded node of level k
+    -- the A children of each kept node of level k-1, in that order -- as
+    (a0, path, positions, stack, reward, R64, R32); kept is None for an
+    uncut level, else the indices (into nodes) of the survivors, root action
+    by root action, ascending."""
+    gps = level_discounts_f32(gamma, d)
+    out = []
+    level = [(a, [a], p1, s1, r, float(r), ret_step_f32(0.0, gps[0], r))
+             for a, (p1, s1, r) in enumerate(children(world, pos, stack, A))]
+    for k in range(1, d + 1):
+        if k > 1:
+            nxt = []
+            for (a0, path, pk, sk, _, R64, R32) in level:
+                for a, (p1, s1, r) in enumerate(children(world, pk, sk, A)):
+                    nxt.append((a0, path + [a], p1, s1, r, R64 + gamma ** (k - 1) * r, ret_step_f32(R32, gps[k - 1], r)))
+            level = nxt
+        kept = None
+        if beam > 0 and 2 <= k <= d - 1:
+            blocks = [[i for i, nd in enumerate(level) if nd[0] == a0] for a0 in range(A)]
+            if any(len(b) > beam for b in blocks):
+                kept = []
+                for blk in blocks:
+                    if len(blk) > beam:
+                        blk = sorted(sorted(blk, key=lambda i: (-level[i][6], i))[:beam])
+                    kept.extend(blk)
+        out.append((level, kept))
+        if kept is not None:
+            level = [level[i] for i in kept]
     return out
-
-
-def ret_step_f32(prev: float, gp: float, r: int) -> float:
-    """FP32 return of a child: fma(gp, r, prev) rounded once (the product of
-    an FP32 discount and a reward <= 7 and its sum with an FP32 return are
-    exact in FP64, so one rounding to FP32 is the fused multiply-add)."""
-    return float(np.float32(np.float64(prev) + np.float64(gp) * np.float64(r)))
 
 
 def search_beam(world: World, pos, stack, d: int, A: int, gamma: float, beam: int,
@@ -220,32 +279,14 @@ def search_beam(world: World, pos, stack, d: int, A: int, gamma: float, beam: in
     here: the tree grows level by level as in Alg. 1; at every level
     k = 2..d-1, inside each root action's sub-tree, only the `beam` nodes
     with the largest discounted return so far are expanded further (ties:
-    lowest index; the ranking uses the library's FP32 returns, so both sides
+    lowest index; ranked on the FP32 returns of the rule above, so both sides
     take the same decision); the leaves are all children of the kept
     level-(d-1) nodes.  Q_d(a0) is the max over a0's surviving leaves of
     R + gamma^d max_a Q (FP64); the depth-0/1 quantities of the correction
     are untouched.  beam = 0 is the exhaustive search."""
     if beam == 0 or d <= 2:
         return search(world, pos, stack, d, A, gamma, correction, c, mode)
-    gps = level_discounts_f32(gamma, d)
-    # a node: (a0, positions, stack, R64, R32); level 1 = the root's children
-    level = []
-    for a, (p1, s1, r) in enumerate(children(world, pos, stack, A)):
-        level.append((a, p1, s1, float(r), ret_step_f32(0.0, gps[0], r)))
-    for k in range(2, d + 1):
-        nxt = []
-        for (a0, pk, sk, R64, R32) in level:
-            for a, (p1, s1, r) in enumerate(children(world, pk, sk, A)):
-                nxt.append((a0, p1, s1, R64 + gamma ** (k - 1) * r, ret_step_f32(R32, gps[k - 1], r)))
-        if k <= d - 1:
-            kept = []
-            for a0 in range(A):
-                blk = [i for i, nd in enumerate(nxt) if nd[0] == a0]
-                if len(blk) > beam:
-                    blk = sorted(sorted(blk, key=lambda i: (-nxt[i][4], i))[:beam])
-                kept.extend(blk)
-            nxt = [nxt[i] for i in kept]
-        level = nxt
+    level = [(nd[0], nd[2], nd[3], nd[5], nd[6]) for nd in beam_levels(world, pos, stack, d, A, gamma, beam)[-1][0]]
     qd = np.full(A, -np.inf)
     stacks = np.stack([nd[2] for nd in level])
     vmax = Q.qvalues(stacks, world.w64, A).max(axis=1)

@@ -42,7 +42,7 @@ EXPORTS = (
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
     "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
     "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc", "bcts_serve_stats",
-    "bcts_debug_fail_launches",
+    "bcts_debug_fail_launches", "bcts_debug_expand_batch",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32, TUNE_MLP_CROSSOVER = 0, 1, 2, 3, 4, 5
 
@@ -92,6 +92,8 @@ _progress = _sig("bcts_progress", c_int32, _P, POINTER(c_int32))
 _poll = _sig("bcts_poll", c_int32, _P, c_uint64, POINTER(c_int32), _P, POINTER(c_double))
 _serve_config = _sig("bcts_serve_config", c_int32, _P, c_int32, c_int32)
 _serve_stats = _sig("bcts_serve_stats", c_int32, _P, _P)
+_debug_expand_batch = _sig("bcts_debug_expand_batch", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, _P, _P, _P, _P,
+                           _P, _P, _P, _P)
 _debug_fail_launches = _sig("bcts_debug_fail_launches", c_int32, _P, c_int32)
 _request_bytes = _sig("bcts_request_bytes", c_size_t, c_int32, c_int32)
 _debug_expand = _sig("bcts_debug_expand", c_int32, _P, _P, _P, c_int32, c_int32, _P, _P, _P)
@@ -337,6 +339,40 @@ def bcts_debug_expand(ctx, pos, stack, depth: int, A: int):
         out.append((op[at:at + nk], of[at:at + nk], orw[at:at + nk]))
         at += nk
     return out
+
+
+def bcts_debug_expand_batch(ctx, pos, stacks, depth, A, gamma: float):
+    """(levels, root_levels): levels[k] = (pos [N][8][2], frames [N][84][84],
+    rewards [N], returns [N], keep [K]) for k = 1..max depth; root_levels
+    [n][7][3] = (first node, node count, first keep entry or -1) per root
+    and level."""
+    n = len(depth)
+    p = _arr(pos, np.int32, (n, 8, 2))
+    s = _arr(stacks, np.uint8, (n, 4, 84, 84))
+    d = _arr(depth, np.int32)
+    a = _arr(A, np.int32)
+    ln = np.zeros(7, np.int64)
+    ke = np.zeros(7, np.int64)
+    rl = np.zeros((n, 7, 3), np.int64)
+    _check(ctx, _debug_expand_batch(ctx, n, _ptr(p), _ptr(s), _ptr(d), _ptr(a), gamma, _ptr(ln), _ptr(ke),
+                                    _ptr(rl), None, None, None, None, None))
+    tot, ktot = int(ln.sum()), int(ke.sum())
+    op = np.zeros((tot, 8, 2), np.int32)
+    of = np.zeros((tot, 84, 84), np.uint8)
+    orw = np.zeros(tot, np.int32)
+    ort = np.zeros(tot, np.float32)
+    ok = np.zeros(max(ktot, 1), np.int32)
+    _check(ctx, _debug_expand_batch(ctx, n, _ptr(p), _ptr(s), _ptr(d), _ptr(a), gamma, _ptr(ln), _ptr(ke),
+                                    _ptr(rl), _ptr(op), _ptr(of), _ptr(orw), _ptr(ort), _ptr(ok)))
+    levels, at, kat = {}, 0, 0
+    for k in range(1, 7):
+        nk, kk = int(ln[k]), int(ke[k])
+        if nk == 0:
+            continue
+        levels[k] = (op[at:at + nk], of[at:at + nk], orw[at:at + nk], ort[at:at + nk], ok[kat:kat + kk])
+        at += nk
+        kat += kk
+    return levels, rl
 
 
 def bcts_debug_qnet(ctx, stacks, A: int) -> np.ndarray:

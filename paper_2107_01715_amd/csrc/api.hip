@@ -324,7 +324,7 @@ bcts_status enqueue_level(bcts_ctx* c, const Plan& p, char* A, int k, const int3
   bcts_status st = launch_gate(c);
   if (st != BCTS_OK) return st;
   const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
-  const float g = (float)std::pow((double)gamma, (double)(k - 1));
+  const float g = discount_f32(gamma, k - 1);    // the FP32 discount a pruned search ranks by
   LevelRoots lr{reinterpret_cast<const int*>(A + p.o_lroot[k]), reinterpret_cast<const long long*>(A + p.o_lstart[k]),
                 (int)p.lvl_root[k].size()};
   launch_expand(k, p.lvl_count[k], lr, roots, d_pos,
@@ -1405,6 +1405,71 @@ bcts_status bcts_debug_expand(bcts_ctx* c, const int32_t* pos, const uint8_t* st
     at += nk;
   }
   (void)stack;
+  return BCTS_OK;
+}
+
+bcts_status bcts_debug_expand_batch(bcts_ctx* c, int32_t n, const int32_t* pos, const uint8_t* stacks,
+                                    const int32_t* depth, const int32_t* A, float gamma, int64_t* level_nodes,
+                                    int64_t* keep_entries, int64_t* root_levels, int32_t* out_pos,
+                                    uint8_t* out_frames, int32_t* out_reward, float* out_ret, int32_t* out_keep) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  bcts_correction off{0, 0.f, 0};
+  if ((st = validate_common(c, n, gamma, off)) != BCTS_OK) return st;
+  if (!pos || !stacks || !depth || !A || !level_nodes || !keep_entries || !root_levels)
+    return fail(c, BCTS_E_INVAL, "NULL buffer");
+  for (int r = 0; r < n; ++r)
+    if ((st = validate_shape(c, A[r], depth[r], off)) != BCTS_OK) return st;
+  if ((st = validate_pos(c, n, pos)) != BCTS_OK) return st;
+  Plan p;
+  make_plan(p, n, depth, A, gamma, off, kMaxA, c->chunk_items, P_FP32, true, false, c->beam, false, c->chunk_items);
+  for (int k = 0; k <= kMaxD; ++k) {
+    level_nodes[k] = k >= 1 && k <= p.maxd ? p.lvl_count[k] : 0;
+    keep_entries[k] = k >= 1 && k <= p.maxd ? p.keep_count[k] : 0;
+  }
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k <= kMaxD; ++k) {
+      int64_t* e = root_levels + ((size_t)r * (kMaxD + 1) + k) * 3;
+      const bool in = k >= 1 && k <= p.roots[r].d;
+      e[0] = in ? p.roots[r].base[k] : -1;
+      e[1] = in ? p.roots[r].lcnt[k] : 0;
+      e[2] = in ? p.roots[r].kbase[k] : -1;
+    }
+  if (!out_pos) return BCTS_OK;                  // sizes only
+  if (!out_frames || !out_reward || !out_ret || !out_keep) return fail(c, BCTS_E_INVAL, "NULL buffer");
+  HIPCHECK(c, hipSetDevice(c->device));
+  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
+  hipStream_t s = c->stream;
+  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->arena + p.o_root_pos, pos, sizeof(int32_t) * n * kSprites * 2, hipMemcpyHostToDevice,
+                             s));
+  for (int k = 1; k <= p.maxd; ++k)
+    if ((st = enqueue_level(c, p, c->arena, k, reinterpret_cast<const int32_t*>(c->arena + p.o_root_pos), gamma, s)) !=
+        BCTS_OK)
+      return st;
+  HIPCHECK(c, hipGetLastError());
+  HIPCHECK(c, hipStreamSynchronize(s));
+  long long at = 0, kat = 0;
+  char* Ar = c->arena;
+  for (int k = 1; k <= p.maxd; ++k) {
+    const long long nk = p.lvl_count[k];
+    std::vector<uint8_t> pb((size_t)nk * 16), rb((size_t)nk);
+    HIPCHECK(c, hipMemcpy(pb.data(), Ar + p.o_pos[k], pb.size(), hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(rb.data(), Ar + p.o_rew[k], rb.size(), hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(out_ret + at, Ar + p.o_ret[k], sizeof(float) * (size_t)nk, hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(out_frames + at * kFrameBytes, Ar + p.o_frames[k], (size_t)nk * kFrameBytes,
+                          hipMemcpyDeviceToHost));
+    if (p.keep_count[k] > 0)
+      HIPCHECK(c, hipMemcpy(out_keep + kat, Ar + p.o_keep[k], sizeof(int) * (size_t)p.keep_count[k],
+                            hipMemcpyDeviceToHost));
+    for (long long i = 0; i < nk; ++i) {
+      for (int q = 0; q < 16; ++q) out_pos[(at + i) * 16 + q] = pb[i * 16 + q];
+      out_reward[at + i] = rb[i];
+    }
+    at += nk;
+    kat += p.keep_count[k];
+  }
+  (void)stacks;
   return BCTS_OK;
 }
 

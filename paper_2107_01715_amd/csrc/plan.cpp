@@ -40,6 +40,29 @@ void gev_coeffs(int A, int d, double* pe, double* po) {
   *po = gev_bias(no) / std::sqrt(2.0);
 }
 
+float discount_f32(float g, int n) {
+  // g = m 2^e with a 24-bit integer m; m^n has at most 120 bits, so the power
+  // is exact in 128-bit integers; keep its top 24 bits, round to nearest even
+  if (n == 0) return 1.0f;
+  int e = 0;
+  const float fr = std::frexp(g, &e);                      // g = fr 2^e, fr in [0.5, 1)
+  const unsigned long long m = (unsigned long long)std::ldexp((double)fr, 24);   // exact: 24 bits
+  e -= 24;
+  unsigned __int128 p = 1;
+  for (int i = 0; i < n; ++i) p *= m;
+  int bits = 0;
+  for (unsigned __int128 t = p; t; t >>= 1) ++bits;
+  int shift = bits - 24, ex = e * n;
+  if (shift > 0) {
+    const unsigned __int128 half = (unsigned __int128)1 << (shift - 1), rem = p & (((unsigned __int128)1 << shift) - 1);
+    unsigned __int128 q = p >> shift;
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    p = q;
+    ex += shift;
+  }
+  return (float)std::ldexp((double)(unsigned long long)p, ex);   // p < 2^25 and the exponent in range: exact
+}
+
 size_t qnet_workspace_bytes(long long chunk, int prec) {
   const size_t el = prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1;
   return (size_t)chunk * (12800 + 5184 + 3136 + 512) * el + 256;

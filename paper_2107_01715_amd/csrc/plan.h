@@ -29,6 +29,11 @@ void gev_coeffs(int A, int d, double* pe, double* po);
 // z with Phi(z) = 1 - p for an upper tail p <= 1/2.
 double probit_upper_tail(double p);
 
+// The FP32 discount of a level-(n+1) reward: the FP32 value nearest to the
+// exact n-th power of g (ties to even), for finite g > 0 and 0 <= n <= 5.
+// A pruned search ranks nodes by FP32 returns formed with these discounts.
+float discount_f32(float g, int n);
+
 // Workspace of the layer-by-layer Q-network path for `chunk` stacks, and of
 // the fused path (x3 in fc1's tiles, h).
 size_t qnet_workspace_bytes(long long chunk, int prec);

@@ -320,7 +320,36 @@ static void coefficients() {
     }
 }
 
+static void discounts() {
+  // exact cases: powers of 1/2 and 1
+  for (int n = 0; n <= 5; ++n) {
+    CHECK(discount_f32(0.5f, n) == std::ldexp(1.0f, -n), "0.5^%d", n);
+    CHECK(discount_f32(1.0f, n) == 1.0f, "1^%d", n);
+  }
+  // g^2 has 48 significant bits, exact in double: one rounding to float
+  Rng rg(7);
+  for (int t = 0; t < 20000; ++t) {
+    const float g = (float)((double)(rg.next() >> 11) * 0x1.0p-53);
+    if (!(g > 0.f)) continue;
+    CHECK(discount_f32(g, 1) == g, "g^1");
+    CHECK(discount_f32(g, 2) == (float)((double)g * (double)g), "g^2 for g = %a", g);
+    // higher powers: the nearest float to the long-double power (64-bit
+    // mantissa), skipping values too close to a rounding boundary to decide
+    for (int n = 3; n <= 5; ++n) {
+      long double pw = 1.0L;
+      for (int i = 0; i < n; ++i) pw *= (long double)g;
+      const float f = (float)pw;
+      const long double up = (long double)std::nextafter(f, 1.0f), dn = (long double)std::nextafter(f, 0.0f);
+      const long double lo = ((long double)f + dn) / 2, hi = ((long double)f + up) / 2;
+      if (std::fabs((double)((pw - lo) / pw)) < 1e-15 || std::fabs((double)((hi - pw) / pw)) < 1e-15) continue;
+      CHECK(discount_f32(g, n) == f, "g^%d for g = %a", n, g);
+    }
+  }
+  CHECK(discount_f32(0.99f, 2) == (float)(0.99f * (double)0.99f), "0.99^2");
+}
+
 int main() {
+  discounts();
   coefficients();
   single_requests();
   plans(1, 400);

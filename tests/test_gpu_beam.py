@@ -1,4 +1,5 @@
-"""Pruned search on the GPU (through the C ABI): FP32 parity with the oracle's
+"""Pruned search on the GPU (through the C ABI): bit-exact expansion and keep
+lists of mixed batches against the oracle's levels, FP32 parity with the oracle's
 pruned search (oracle.search.search_beam, same FP32 ranking), bit-identity
 with the exhaustive search when the beam cuts nothing, the sub-tree bound
 (a pruned root value never exceeds the exhaustive one; both paths score the
@@ -126,3 +127,54 @@ def test_beam_argument(lib, setup):
         with pytest.raises(lib.BctsError) as e:
             ctx.set_beam(bad)
         assert e.value.status == lib.E_INVAL
+
+
+def _check_root_levels(levels, rl, r, ref_levels, tag):
+    """Root r's nodes of every level against the oracle's, bit for bit:
+    positions, frames, rewards, the FP32 return, and the keep list."""
+    for k, (ref_nodes, ref_kept) in enumerate(ref_levels, start=1):
+        gp, gf, gr, gret, gkeep = levels[k]
+        base, cnt, kbase = (int(v) for v in rl[r, k])
+        assert cnt == len(ref_nodes), (tag, k, cnt, len(ref_nodes))
+        sl = slice(base, base + cnt)
+        want_pos = np.array([nd[2] for nd in ref_nodes], dtype=np.int32)
+        want_frames = np.array([nd[3][-1] for nd in ref_nodes], dtype=np.uint8)
+        want_rew = np.array([nd[4] for nd in ref_nodes], dtype=np.int32)
+        want_ret = np.array([nd[6] for nd in ref_nodes], dtype=np.float32)
+        assert np.array_equal(gp[sl], want_pos), (tag, k, "positions")
+        assert np.array_equal(gr[sl], want_rew), (tag, k, "rewards")
+        bad = np.flatnonzero((gf[sl] != want_frames).reshape(cnt, -1).any(axis=1))
+        assert bad.size == 0, (tag, k, "frames", bad[:8])
+        assert np.array_equal(gret[sl], want_ret), (tag, k, "FP32 returns")
+        if ref_kept is None:
+            assert kbase == -1, (tag, k)
+        else:
+            got = gkeep[kbase:kbase + len(ref_kept)]
+            assert np.array_equal(got, ref_kept), (tag, k, "keep list")
+
+
+@pytest.mark.parametrize("beam", [0, 2, 5])
+def test_batch_expansion_bit_exact(lib, setup, beam):
+    """A batch of roots of mixed A and depth expanded in one launch per level
+    (and, with a beam, cut): every root's nodes at every level against the
+    oracle's nodes of the same rule (search.beam_levels, exhaustive when
+    nothing is cut): positions, frames, rewards and FP32 returns bit for
+    bit, keep lists equal."""
+    ctx, world = setup
+    A = np.array([4, 18, 2, 6, 3, 4, 18, 6], np.int32)
+    d = np.array([3, 2, 5, 3, 4, 1, 3, 2], np.int32)
+    pos, st = W.roots(1006, len(A))
+    ctx.set_beam(beam)
+    try:
+        levels, rl = ctx.debug_expand_batch(pos, st, d, A, GAMMA)
+    finally:
+        ctx.set_beam(0)
+    for r in range(len(A)):
+        ref = S.beam_levels(world, pos[r], st[r], int(d[r]), int(A[r]), GAMMA, beam)
+        _check_root_levels(levels, rl, r, ref, f"root {r} (A={A[r]}, d={d[r]}, beam={beam})")
+    if beam == 0:                                  # the exhaustive order of Alg. 1 for one root too
+        want = S.enumerate_nodes(world, pos[0], st[0], int(d[0]), int(A[0]))
+        for k in range(1, int(d[0]) + 1):
+            base, cnt, _ = (int(v) for v in rl[0, k])
+            assert np.array_equal(levels[k][0][base:base + cnt], want[k - 1][0])
+            assert np.array_equal(levels[k][1][base:base + cnt], want[k - 1][1])

@@ -5,6 +5,9 @@ an independent re-derivation of the rule over sets of action prefixes, and
 the bound that a search over a sub-tree never exceeds the exhaustive one."""
 import itertools
 
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -105,11 +108,54 @@ def test_cut_never_exceeds_exhaustive_and_changes_something(world):
     assert changed > 0, "the cut should bind for some root at beam 1"
 
 
-def test_fp32_discounts_and_fma():
-    gps = S.level_discounts_f32(0.99, 4)
-    assert gps[0] == 1.0 and abs(gps[3] - 0.99 ** 3) < 1e-7
-    assert all(np.float32(g) == g for g in gps)
-    # one rounding: 0.1f + 0.99f * 7 differs from rounding the product first when they disagree
-    x = S.ret_step_f32(float(np.float32(0.1)), gps[1], 7)
-    assert np.float32(x) == x
-    assert x == float(np.float32(np.float64(np.float32(0.1)) + np.float64(gps[1]) * 7.0))
+def _nearest_f32(exact: Decimal) -> float:
+    """The FP32 value nearest to `exact` by direct comparison with the
+    neighbours of a first guess (an independent route to the rounding);
+    asserts the nearest is unique (no tie)."""
+    guess = np.float32(float(exact))
+    cands = [np.nextafter(guess, np.float32(-np.inf)), guess, np.nextafter(guess, np.float32(np.inf))]
+    dist = sorted((abs(Decimal(float(c)) - exact), float(c)) for c in cands)
+    assert dist[0][0] < dist[1][0]
+    return dist[0][1]
+
+
+def test_fp32_discounts_of_the_rule():
+    """d_k = RN32(g^(k-1)), g the FP32 gamma.  Powers of 1/2 and 1 are exact;
+    for gamma = 0.99: d_2 = float32(0.99) (0x3F7D70A4); g^2 has 48
+    significant bits, exact in binary64, so d_3 = float32(g * g computed in
+    binary64); d_4 by nearest-neighbour search against the exact decimal
+    value of g^3."""
+    assert S.level_discounts_f32(0.5, 4) == [1.0, 0.5, 0.25, 0.125]
+    assert S.level_discounts_f32(1.0, 3) == [1.0, 1.0, 1.0]
+    d = S.level_discounts_f32(0.99, 4)
+    g = np.float32(0.99)
+    assert int(g.view(np.uint32)) == 0x3F7D70A4
+    assert d[0] == 1.0 and d[1] == float(g)
+    assert d[2] == float(np.float32(np.float64(g) * np.float64(g)))
+    getcontext().prec = 80
+    assert d[3] == _nearest_f32(Decimal(float(g)) ** 3)
+    assert all(float(np.float32(x)) == x for x in d)
+
+
+def test_fp32_return_is_one_rounding():
+    """R_k = RN32(R_{k-1} + d_k r): on FP32 inputs where rounding the product
+    first gives another value (14.734909057617188), the rule keeps the value
+    nearest to the exact sum (checked by neighbour search)."""
+    prev = float(np.uint32(0x41002BFB).view(np.float32))
+    dk = float(np.uint32(0x3F75E99F).view(np.float32))
+    assert (prev, dk) == (8.010737419128418, 0.9605960249900818)
+    got = S.ret_step_f32(prev, dk, 7)
+    assert got == _nearest_f32(Decimal(prev) + Decimal(dk) * 7) == 14.734910011291504
+    assert float(np.float32(prev + float(np.float32(dk * 7)))) == 14.734909057617188   # two roundings
+    # simple exact cases
+    assert S.ret_step_f32(0.0, 1.0, 3) == 3.0 and S.ret_step_f32(1.75, 0.25, 1) == 2.0
+
+
+def test_round_f32_matches_numpy_on_doubles():
+    """RN32 of an exact rational equals numpy's float64 -> float32
+    conversion (a library routine) on random doubles, ties included."""
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.standard_normal(3000) * 10.0 ** rng.integers(-6, 6, 3000),
+                        np.array([1.0 + 2.0 ** -24, 1.0 + 3 * 2.0 ** -24, 3.0 * 2.0 ** -25, -(1.0 + 2.0 ** -24)])])
+    for v in x:
+        assert S.round_f32(Fraction(float(v))) == float(np.float32(v)), v
