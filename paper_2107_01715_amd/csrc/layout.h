@@ -35,6 +35,9 @@ BCTS_HD inline long long fc1_tiled_offset(long long r, int kb, int eb) {
 }
 inline long long fc1_padded_rows(long long n) { return (n + kFc1Rows - 1) / kFc1Rows * kFc1Rows; }
 
+// K slices of the FP32 fc1 (its 98 K stages of 32 split evenly).
+constexpr int kFc1Split = 7;
+
 // Precisions (mirrors bcts_precision).
 enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
 

@@ -65,7 +65,8 @@ float discount_f32(float g, int n) {
 
 size_t qnet_workspace_bytes(long long chunk, int prec) {
   const size_t el = prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1;
-  return (size_t)chunk * (12800 + 5184 + 3136 + 512) * el + 256;
+  const size_t part = prec == P_FP32 ? (size_t)chunk * kFc1Split * 512 * 4 : 0;   // fc1's K slices
+  return (size_t)chunk * (12800 + 5184 + 3136 + 512) * el + part + 256;
 }
 
 // fused path: x3 [chunk rounded up to fc1's 256-row tiles][3136] and

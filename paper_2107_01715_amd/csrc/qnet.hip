@@ -283,6 +283,7 @@ struct LayerArgs {
   void* out;                   // C (conv1..fc1)
   float* V;                    // fc2: max_a Q per item
   float* q0;                   // fc2: [n_roots][18]
+  float* part;                 // FP32 fc1: the K slices' partial sums [kFc1Split][M][512]
 };
 
 template <int L, int P>
@@ -339,14 +340,19 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
     }
   };
 
-  gload(0);
+  // FP32 fc1 runs K in kFc1Split slices, one per blockIdx.z (see run_layer)
+  constexpr bool kSplit = (L == 3 && P == P_FP32);
+  static_assert(!kSplit || NSTAGE % kFc1Split == 0, "fc1's stages split evenly");
+  const int st0 = kSplit ? (int)blockIdx.z * (NSTAGE / kFc1Split) : 0;
+  const int st1 = kSplit ? st0 + NSTAGE / kFc1Split : NSTAGE;
+  gload(st0);
   lstore();
   lds_barrier();
-  for (int st = 0; st < NSTAGE; ++st) {
-    if (st + 1 < NSTAGE) gload(st + 1);
+  for (int st = st0; st < st1; ++st) {
+    if (st + 1 < st1) gload(st + 1);
     mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
     lds_barrier();
-    if (st + 1 < NSTAGE) {
+    if (st + 1 < st1) {
       lstore();
       lds_barrier();
     }
@@ -354,7 +360,21 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
 
   // epilogue: lane holds rows 4*(lane>>4) + q, column lane & 15 of each frag
   const int col = lane & 15, rq = (lane >> 4) * 4;
-  if constexpr (L < 4) {
+  if constexpr (kSplit) {
+    // the slice's raw partial sums; fc1_reduce_kernel adds the slices in order
+    float* part = args.part + (long long)blockIdx.z * args.M * Geo<L>::N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const int n = n0 + j * 16 + col;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long long m = m0 + wave * 32 + i * 16 + rq + q;
+          if (m < args.M) part[m * Geo<L>::N + n] = acc[i][j][q];
+        }
+      }
+  } else if constexpr (L < 4) {
     T* out = reinterpret_cast<T*>(args.out);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -399,11 +419,32 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
   }
 }
 
+// FP32 fc1: h = ReLU((part_0 + part_1 + ... in slice order) * scale + b)
+__global__ void fc1_reduce_kernel(long long M, const float* __restrict__ part, const float* __restrict__ bias,
+                                  float scale, float* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * 512) return;
+  float v = part[t];
+  for (int z = 1; z < kFc1Split; ++z) v += part[z * M * 512 + t];
+  out[t] = fmaxf(v * scale + bias[t % 512], 0.f);
+}
+
+// FP32 fc1 (K = 3136, 98 stages) splits K into kFc1Split slices, each its
+// own workgroup, then sums the slices in a fixed order: a small batch (the
+// correction's FP32 evaluations of a few roots) then runs 7x more
+// workgroups instead of one long serial K loop, and every row's sum order
+// stays fixed whatever the batch.
 template <int L, int P>
 void run_layer(const LayerArgs& a, hipStream_t s) {
   const long long blocks = (a.M + kBM - 1) / kBM;
-  dim3 grid((unsigned)blocks, Geo<L>::N / Geo<L>::BN);
+  constexpr bool split = (L == 3 && P == P_FP32);
+  dim3 grid((unsigned)blocks, Geo<L>::N / Geo<L>::BN, split ? kFc1Split : 1);
   hipLaunchKernelGGL((layer_kernel<L, P>), grid, dim3(kThreads), 0, s, a);
+  if (split) {
+    const long long t = a.M * 512;
+    hipLaunchKernelGGL(fc1_reduce_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, a.M, a.part, a.bias,
+                       a.acc_scale, reinterpret_cast<float*>(a.out));
+  }
 }
 
 // item descriptors: the 4 frames of each item's stack
@@ -452,6 +493,7 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, flo
   T* x2 = x1 + n * 12800;
   T* x3 = x2 + n * 5184;
   T* h = x3 + n * 3136;
+  float* part = reinterpret_cast<float*>(h + n * 512);    // FP32: fc1's K slices
   auto wp = [&](int l) -> const void* {
     return P == P_FP32 ? (const void*)q.w[l] : P == P_BF16 ? (const void*)q.wb[l] : (const void*)q.w8[l];
   };
@@ -475,6 +517,7 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, flo
   run_layer<2, P>(a, s);
   if (ev) (void)hipEventRecord(ev[3], s);
   a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3); a.out_s8 = outs(3); a.out = h;
+  a.part = part;
   run_layer<3, P>(a, s);
   if (ev) (void)hipEventRecord(ev[4], s);
   a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
