@@ -22,6 +22,9 @@ Bars (relative to each stack's / root's largest |Q|):
   e4m3 rounding boundary; one e4m3 step is 2^-3 = 12.5% of the activation
   it rounds, so such a flip moves Q by up to a few per cent, and flips are
   rare, which the count bound checks.
+Against the FP64 search every root also meets a max bound: its error is at
+most the emulation's own distance from FP64 (the operand rounding alone,
+computed by the oracle) plus the emulation bar.
 Root actions must agree with the emulated search's, up to actions whose
 values lie within the root's measured error of the best one.  Where
 the FP64 root values are themselves within FP32 rounding of a tie for pi_o,
@@ -125,7 +128,8 @@ def _lowp_root(args):
         pos, st = W.roots(seed, n)
         res = S.search_lowp(world, pos[r], st[r], d, A, GAMMA, prec, ascale=ascale)
         ref = S.search(world, pos[r], st[r], 0, A, GAMMA)         # FP64 root values (pi_o)
-        return res.q, res.action, res.ties, ref.q
+        full = S.search(world, pos[r], st[r], d, A, GAMMA)        # the FP64 search itself
+        return res.q, res.action, res.ties, ref.q, full.q
 
 
 def lowp_refs(seed, n, roots, d, A, prec, ascale):
@@ -136,8 +140,22 @@ def lowp_refs(seed, n, roots, d, A, prec, ascale):
 
 
 def compare_roots(act, q, refs, Avec, prec, what):
+    """Against the emulated search (the bars above) and, per root, a max
+    bound against the FP64 search: the GPU's distance from FP64 is at most
+    the emulation's own (the operand rounding, computed by the oracle) plus
+    the emulation bar."""
     rels, excused = [], 0
-    for i, (qo, ao, ties, q0) in enumerate(refs):
+    far = []
+    for i, (qo, ao, ties, q0, q64) in enumerate(refs):
+        A = int(Avec[i])
+        q64 = np.asarray(q64)
+        scale = np.abs(q64).max()
+        e_gpu = np.abs(q[i, :A].astype(np.float64) - q64).max() / scale
+        e_emu = np.abs(np.asarray(qo) - q64).max() / scale
+        far.append(e_gpu)
+        assert e_gpu <= e_emu + BARS[prec]["mx"], (what, i, e_gpu, e_emu)
+    print(f"{prec} {what}: max error against FP64 {max(far):.3g} (mean {np.mean(far):.3g})")
+    for i, (qo, ao, ties, q0, _) in enumerate(refs):
         A = int(Avec[i])
         qo = np.asarray(qo)
         top = np.sort(q0)[-2:]
