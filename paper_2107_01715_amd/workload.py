@@ -126,9 +126,17 @@ def paint_sprites(pos: np.ndarray) -> np.ndarray:
 def roots(seed: int, n: int) -> tuple[np.ndarray, np.ndarray]:
     """n root states: positions int32 [n][8][2] (x, y in [0,84)) and frame
     stacks uint8 [n][4][84][84] (channel 0 oldest).  The newest frame shows
-    the root positions; the three older frames show seeded positions."""
-    hist = ints(seed, "roots.pos", n * STACK * N_SPRITES * 2, FRAME)
-    hist = hist.reshape(n, STACK, N_SPRITES, 2).astype(np.int32)
+    the root positions (uniform); each older frame shows every sprite moved
+    back by a seeded offset in [-3, 3]^2 (wrapping), so a stack looks like
+    the last steps of a trajectory, as an agent's frame stack does.  (The
+    offsets are drawn here; the world's own transition is not used.)"""
+    pos = ints(seed, "roots.pos", n * N_SPRITES * 2, FRAME).reshape(n, N_SPRITES, 2).astype(np.int64)
+    back = ints(seed, "roots.back", n * (STACK - 1) * N_SPRITES * 2, 7).reshape(n, STACK - 1, N_SPRITES, 2) - 3
+    hist = np.empty((n, STACK, N_SPRITES, 2), dtype=np.int64)
+    hist[:, STACK - 1] = pos
+    for c in range(STACK - 2, -1, -1):
+        hist[:, c] = (hist[:, c + 1] - back[:, c]) % FRAME
+    hist = hist.astype(np.int32)
     pos = np.ascontiguousarray(hist[:, STACK - 1])
     stacks = np.empty((n, STACK, FRAME, FRAME), dtype=np.uint8)
     for r in range(n):

@@ -42,6 +42,16 @@ def test_roots_structure():
         assert np.array_equal(st[r, 3], E.render(pos[r]))   # newest frame shows the root
         for c in range(4):
             assert int((st[r, c] == 255).sum()) == 36
+        # older frames: sprite 0's 6x6 square moved by at most 3 pixels per step
+        def anchor(frame):
+            ys, xs = np.nonzero(frame == 255)
+            cy, cx = set(ys.tolist()), set(xs.tolist())
+            return ([y for y in cy if (y - 1) % 84 not in cy][0], [x for x in cx if (x - 1) % 84 not in cx][0])
+        y3, x3 = anchor(st[r, 3])
+        for c in range(3):
+            y, x = anchor(st[r, c])
+            for dlt in ((y - y3) % 84, (x - x3) % 84):
+                assert min(dlt, 84 - dlt) <= 3 * (3 - c), (r, c, dlt)
 
 
 def test_request_stream_mix():
