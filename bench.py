@@ -592,13 +592,14 @@ def main():
             ctx.set_tuning(bcts.TUNE_FUSED, best["fused"])
             ctx.set_tuning(bcts.TUNE_FUSED_ROUND, best["round"])
             ctx.set_tuning(bcts.TUNE_FUSED_CHUNK, best["chunk"])
+            ctx.set_tuning(bcts.TUNE_FP8_K128, best.get("fp8_k128", 1))
         else:
             with torch.cuda.stream(stream):
                 best = ctx.autotune(pos_t, st_t, depth, Av, GAMMA, corr, act_t, q_t, reps=2, stream=stream)
             torch.cuda.synchronize()
-            cache[key] = {k: int(best[k]) for k in ("fused", "round", "chunk")}
+            cache[key] = {k: int(best[k]) for k in ("fused", "round", "chunk", "fp8_k128")}
             cache[key]["us_per_search"] = best.get("us_per_search")
-        tuned_all[prec] = {k: best[k] for k in ("fused", "round", "chunk")}
+        tuned_all[prec] = {k: best.get(k, 1) for k in ("fused", "round", "chunk", "fp8_k128")}
         tuned_all[prec]["us_per_search"] = best.get("us_per_search")
         print(f"# autotune {prec}: {best}", file=sys.stderr, flush=True)
     tuned = tuned_all.get(args.precision, {})
@@ -616,6 +617,7 @@ def main():
             ctx.set_tuning(bcts.TUNE_FUSED, t["fused"])
             ctx.set_tuning(bcts.TUNE_FUSED_ROUND, t["round"])
             ctx.set_tuning(bcts.TUNE_FUSED_CHUNK, t["chunk"])
+            ctx.set_tuning(bcts.TUNE_FP8_K128, t["fp8_k128"])
 
     print(f"# {args.precision} batched: warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
     # per-kernel HIP-event timing (each step waits for its events) ...

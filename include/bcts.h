@@ -221,23 +221,32 @@ bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_
  *                          the GPU, k = min(value, depth - 1); 0 (default)
  *                          = the whole search on the GPU.  The host levels
  *                          do the device kernel's FP32 arithmetic in the
- *                          same order, so results are the same bits.       */
+ *                          same order, so results are the same bits.
+ *   BCTS_TUNE_FP8_K128     FP8 fused path: 1 (default) = conv2 / conv3 on
+ *                          the K = 128 matrix instruction (rounds of 3..5
+ *                          stacks), 0 = the K = 32 one (rounds of 1..4).
+ *                          The products of each 8 consecutive K values are
+ *                          summed the same way by both, so the results are
+ *                          the same up to FP32 addition order.             */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
   BCTS_TUNE_FUSED_CHUNK = 2,
   BCTS_TUNE_LAYER_CHUNK = 3,
   BCTS_TUNE_CORR_FP32 = 4,
-  BCTS_TUNE_MLP_CROSSOVER = 5
+  BCTS_TUNE_MLP_CROSSOVER = 5,
+  BCTS_TUNE_FP8_K128 = 6
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);
-/* Autotuner: times every candidate (fused or not, round 1..4, chunk 256Ki /
- * 1Mi stacks) on one device batch (arguments as in
- * bcts_search_batch_device; the scratch outputs receive the results),
- * `reps` timed searches each after one warm-up, keeps the fastest setting
- * on the context and returns it: out_best = {fused, round, chunk,
- * microseconds per search}.  Candidates over the HBM budget are skipped.   */
+/* Autotuner: times every candidate -- fused or not, for FP8 the K = 128 or
+ * K = 32 matrix instruction, the round size (stacks per LDS round: the
+ * fused kernel's row tile), chunks of 256Ki / 1Mi stacks -- on one device
+ * batch (arguments as in bcts_search_batch_device; the scratch outputs
+ * receive the results), `reps` timed searches each after one warm-up, keeps
+ * the fastest setting on the context and returns it: out_best [5] = {fused,
+ * round, chunk, microseconds per search, FP8 K = 128}.  Candidates over the
+ * HBM budget are skipped.                                                  */
 bcts_status bcts_autotune(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos, const uint8_t* d_stacks,
                           const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
                           void* d_scratch_action, void* d_scratch_q, int32_t reps, void* hip_stream,

@@ -45,6 +45,7 @@ EXPORTS = (
     "bcts_debug_fail_launches", "bcts_debug_expand_batch",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32, TUNE_MLP_CROSSOVER = 0, 1, 2, 3, 4, 5
+TUNE_FP8_K128 = 6
 
 
 class EnvParamsC(ctypes.Structure):
@@ -410,16 +411,17 @@ def bcts_get_tuning(ctx, key: int) -> int:
 
 
 def bcts_autotune(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, reps=2, stream=None):
-    """Returns {fused, round, chunk, us_per_search} and keeps it on ctx."""
+    """Returns {fused, round, chunk, us_per_search, fp8_k128} and keeps it on ctx."""
     d = _arr(depth, np.int32)
     a = _arr(A, np.int32)
     s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
-    out = (ctypes.c_int64 * 4)()
+    out = (ctypes.c_int64 * 5)()
     n = pos_t.shape[0]
     _check(ctx, _autotune(ctx, n, _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8), _ptr(d),
                           _ptr(a), gamma, corr, _dev(act_t, torch.int32, n), _dev(q_t, torch.float32, n * MAX_A),
                           reps, s, out))
-    return {"fused": int(out[0]), "round": int(out[1]), "chunk": int(out[2]), "us_per_search": int(out[3])}
+    return {"fused": int(out[0]), "round": int(out[1]), "chunk": int(out[2]), "us_per_search": int(out[3]),
+            "fp8_k128": int(out[4])}
 
 
 # ---- convenience object ----------------------------------------------------

@@ -54,6 +54,7 @@ struct bcts_ctx {
   long long chunk_items = 8192;        // layer-by-layer path (FP32)
   long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
+  bool fp8_k128 = true;                 // FP8 conv2 / conv3 on the K = 128 matrix instruction
   bool fused = true;
   bool corr_fp32 = true;                // root / depth-1 evals of corrected roots in FP32
   int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
@@ -364,7 +365,8 @@ bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* de
   const bool f8 = c->prec == P_FP8;
   for (int l = 0; l < 3; ++l) {
     // conv1 in GEMM layout, conv2 / conv3 fragment-major
-    fa.w[l] = l == 0 ? (f8 ? (const void*)q.w8[0] : (const void*)q.wb[0]) : (f8 ? q.wf8[l] : q.wfb[l]);
+    fa.w[l] = l == 0 ? (f8 ? (const void*)q.w8[0] : (const void*)q.wb[0])
+                     : (f8 ? (c->fp8_k128 ? q.wf8k[l] : q.wf8[l]) : q.wfb[l]);
     fa.bias[l] = q.b[l];
     fa.acc_scale[l] = f8 ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f;
     fa.out_s8[l] = f8 ? q.ascale[l + 1] : 1.f;
@@ -375,7 +377,7 @@ bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* de
   char* h = x3 + fused_x3_bytes(p.chunk, c->prec);
   fa.x3 = x3;
   if (cev) HIPCHECK(c, hipEventRecord(cev[0], s));
-  launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s);
+  launch_conv_fused(c->prec, c->fused_T, fa, ch.g1 - ch.g0, s, c->fp8_k128);
   if (cev) {
     HIPCHECK(c, hipEventRecord(cev[1], s));
     HIPCHECK(c, hipEventRecord(cev[2], s));
@@ -1085,7 +1087,7 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
 
   // fp32 w, bf16 w, fp8 w, bias, and for conv2 / conv3 fragment-major (fc1: stage-major tiled)
   // bf16 and fp8 copies
-  size_t off[5][6], o = 0;
+  size_t off[5][7], o = 0;
   for (int l = 0; l < 5; ++l) {
     const size_t n = W[l].size();
     off[l][0] = o; o += align_up(n * 4);
@@ -1095,6 +1097,7 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
     const size_t fc1_tiles = (size_t)(NK[3][0] / kFc1Rows);
     off[l][4] = o; o += (l == 1 || l == 2) ? align_up(n * 2) : l == 3 ? align_up(fc1_tiles * fc1_tile_bytes(2)) : 0;
     off[l][5] = o; o += (l == 1 || l == 2) ? align_up(n) : l == 3 ? align_up(fc1_tiles * fc1_tile_bytes(1)) : 0;
+    off[l][6] = o; o += (l == 1 || l == 2) ? align_up(n) : 0;        // FP8 for the K = 128 instruction
   }
   if (c->wmem) {
     HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -1118,12 +1121,14 @@ bcts_status bcts_set_qnet(bcts_ctx* c, const float* blob, size_t n_floats) {
     launch_convert_bf16(c->q.w[l], const_cast<uint16_t*>(c->q.wb[l]), (long long)W[l].size(), c->stream);
     launch_convert_fp8(c->q.w[l], const_cast<uint8_t*>(c->q.w8[l]), (long long)W[l].size(), c->q.wscale[l],
                        c->stream);
-    c->q.wfb[l] = c->q.wf8[l] = nullptr;
+    c->q.wfb[l] = c->q.wf8[l] = c->q.wf8k[l] = nullptr;
     if (l == 1 || l == 2) {
       c->q.wfb[l] = base + off[l][4];
       c->q.wf8[l] = base + off[l][5];
+      c->q.wf8k[l] = base + off[l][6];
       launch_fragment_major(c->q.wb[l], const_cast<void*>(c->q.wfb[l]), NK[l][0], NK[l][1], 2, true, c->stream);
       launch_fragment_major(c->q.w8[l], const_cast<void*>(c->q.wf8[l]), NK[l][0], NK[l][1], 1, true, c->stream);
+      launch_fragment_major_k128(c->q.w8[l], const_cast<void*>(c->q.wf8k[l]), NK[l][0], NK[l][1], c->stream);
     } else if (l == 3) {
       c->q.wfb[l] = base + off[l][4];
       c->q.wf8[l] = base + off[l][5];
@@ -1676,6 +1681,9 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
       if (value < 1 || value > (1LL << 22)) return fail(c, BCTS_E_INVAL, "layer chunk out of range");
       c->chunk_items = value;
       return BCTS_OK;
+    case BCTS_TUNE_FP8_K128:
+      c->fp8_k128 = value != 0;
+      return BCTS_OK;
     case BCTS_TUNE_MLP_CROSSOVER:
       if (value < 0 || value > kMlpMaxD) return fail(c, BCTS_E_INVAL, "cross-over depth %lld outside [0,%d]",
                                                      (long long)value, kMlpMaxD);
@@ -1698,6 +1706,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_LAYER_CHUNK: *value = c->chunk_items; return BCTS_OK;
     case BCTS_TUNE_CORR_FP32: *value = c->corr_fp32 ? 1 : 0; return BCTS_OK;
     case BCTS_TUNE_MLP_CROSSOVER: *value = c->mlp_crossover; return BCTS_OK;
+    case BCTS_TUNE_FP8_K128: *value = c->fp8_k128 ? 1 : 0; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }
@@ -1710,14 +1719,15 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
   if (st != BCTS_OK) return st;
   if ((st = refuse_if_serving(c, "bcts_autotune")) != BCTS_OK) return st;
   if (reps < 1 || !out_best) return fail(c, BCTS_E_INVAL, "reps >= 1 and out_best required");
-  // candidates: fused on/off (FP32 is never fused), round T, fused chunk size
-  const int Ts[4] = {1, 2, 3, 4};
+  // candidates: fused on/off (FP32 is never fused), the FP8 matrix
+  // instruction (K = 128 or 32), round T, fused chunk size
+  const int Ts[5] = {1, 2, 3, 4, 5};
   const long long chunks[2] = {262144, 1048576};
-  const bool was_fused = c->fused, was_timing = c->timing;
+  const bool was_fused = c->fused, was_timing = c->timing, was_k128 = c->fp8_k128;
   const int was_T = c->fused_T;
   const long long was_chunk = c->fused_chunk_items;
   double best_ms = 1e30;
-  int64_t best[4] = {was_fused, was_T, was_chunk, 0};
+  int64_t best[5] = {was_fused, was_T, was_chunk, 0, was_k128};
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0));
@@ -1727,10 +1737,16 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
   }
   c->timing = false;
   for (int fz = (c->prec == P_FP32 ? 0 : 1); fz >= 0 && st == BCTS_OK; --fz) {
-    for (int ti = 0; ti < (fz ? 4 : 1) && st == BCTS_OK; ++ti) {
-      if (fz && c->prec == P_BF16 && Ts[ti] == 4) continue;   // over the LDS of one CU
+   for (int k8 = (fz && c->prec == P_FP8) ? 1 : 0; k8 >= 0 && st == BCTS_OK; --k8) {
+    for (int ti = 0; ti < (fz ? 5 : 1) && st == BCTS_OK; ++ti) {
+      // rounds the kernel has: BF16 1..3 (4 is over the LDS of one CU), FP8
+      // with K = 32 1..4, with K = 128 3..5
+      if (fz && c->prec == P_BF16 && Ts[ti] > 3) continue;
+      if (fz && c->prec == P_FP8 && !k8 && Ts[ti] > 4) continue;
+      if (fz && k8 && Ts[ti] < 3) continue;
       for (int ci = 0; ci < (fz ? 2 : 1) && st == BCTS_OK; ++ci) {
         c->fused = fz != 0;
+        c->fp8_k128 = k8 != 0;
         c->fused_T = Ts[ti];
         c->fused_chunk_items = chunks[ci];
         st = bcts_search_batch_device(c, n, d_pos, d_stacks, depth, A, gamma, corr,
@@ -1756,9 +1772,11 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
           best[0] = fz;
           best[1] = Ts[ti];
           best[2] = chunks[ci];
+          best[4] = k8;
         }
       }
     }
+   }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1767,15 +1785,18 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
     c->fused = was_fused;
     c->fused_T = was_T;
     c->fused_chunk_items = was_chunk;
+    c->fp8_k128 = was_k128;
     return st;
   }
   c->fused = best[0] != 0;
   c->fused_T = (int)best[1];
   c->fused_chunk_items = best[2];
+  c->fp8_k128 = best[4] != 0;
   out_best[0] = best[0];
   out_best[1] = best[1];
   out_best[2] = best[2];
   out_best[3] = (int64_t)(best_ms * 1000.0);   // microseconds per search
+  out_best[4] = best[4];
   return BCTS_OK;
 }
 

@@ -60,7 +60,8 @@ struct FusedConvArgs {
   float pix_s8;                // fp8: pixel scale
   void* x3;                    // out: [chunk items][49][64] channels-last, in fc1's stage-major tiles
 };
-void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s);
+// k8: FP8 conv2 / conv3 on the K = 128 instruction (weights in wf8k).
+void launch_conv_fused(int prec, int T, const FusedConvArgs& a, int n_groups, hipStream_t s, bool k8 = false);
 
 // Device weights in GEMM layout W[N][K] for every precision.  K orders:
 // conv1 (c, kh, kw); conv2, conv3 (kh, kw, c); fc1 (h, w, c); fc2 (k).
@@ -77,6 +78,7 @@ struct QnetDev {
   // fc1 (index 3) in stage-major tiles for fc1_kernel
   const void* wfb[5];          // bf16
   const void* wf8[5];          // e4m3
+  const void* wf8k[5];         // e4m3, conv2 / conv3 for the K = 128 instruction (launch_fragment_major_k128)
 };
 
 // Learned forward-model world: weights on the device, FP32, [out][in] rows of
@@ -98,6 +100,10 @@ void launch_mlp_root(const MlpDev& m, int n, int d, const float* states, const f
 // interleaved in groups of 4 so each lane group's results are 8 consecutive
 // channels.
 void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, bool pair8, hipStream_t s);
+// The FP8 copy for the K = 128 instruction: per channel fragment, 32 bytes
+// (K 128s + 32(lane/16) .. +31) per lane and step, then 8-byte units for the
+// K % 128 remainder; rows paired as above.
+void launch_fragment_major_k128(const void* src, void* dst, int N, int K, hipStream_t s);
 
 // Copies fc1's W[N][K] (N a multiple of 256, eb bytes per element) into
 // stage-major tiles.

@@ -43,6 +43,8 @@ namespace bcts {
 namespace {
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) int v8i;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
 typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
@@ -52,6 +54,8 @@ constexpr int kF1 = 4;                 // conv1 pixel fragments per wave: w + 8i
 constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
+constexpr int kD8 = 2;                 // K8 weight lookahead in K = 128 steps (requested during conv1)
+constexpr int kRing8 = kD8;
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -175,12 +179,16 @@ template <> struct F<P_FP8> {
 //      ox + kw/2) of phase (kh&1, kw&1): neighbouring output pixels read
 //      neighbouring LDS pixels.
 //  x2: conv2 output 9x9x64, pixel stride 72 elements (64 channels + 8 pad).
-template <int P> struct Lay {
+//  With the FP8 K = 128 instruction (K8) a lane reads 32 consecutive channels
+//  of one pixel per step, two 16-byte reads: pixel strides of 48 (x1) and 80
+//  (x2) bytes keep them aligned, and 3 and 5 16-byte units per pixel put 16
+//  consecutive pixels on distinct bank groups.
+template <int P, bool K8 = false> struct Lay {
   static constexpr int EB = F<P>::EB;
-  static constexpr int X1P = 40 * EB;               // pixel stride
+  static constexpr int X1P = K8 ? 48 : 40 * EB;     // pixel stride
   static constexpr int X1PH = 100 * X1P;            // phase stride
   static constexpr int X1T = 4 * X1PH;              // item stride
-  static constexpr int X2P = 72 * EB;
+  static constexpr int X2P = K8 ? 80 : 72 * EB;
   static constexpr int X2T = 81 * X2P;
   __device__ static int x1(int t, int y, int x, int c) {
     return t * X1T + ((y & 1) * 2 + (x & 1)) * X1PH + ((y >> 1) * 10 + (x >> 1)) * X1P + c * EB;
@@ -192,15 +200,23 @@ template <int P> struct Lay {
 // two wavefronts share each SIMD and cover each other's memory latency.  In
 // conv2 / conv3 wave w takes channel half (w & 1) and pixel fragments
 // (w >> 1) + 4i; their weight fragments stream from L2 kD K steps ahead.
-template <int P, int T>
+//
+// K8 (FP8 only): conv2 and conv3 run on v_mfma_scale_f32_16x16x128_f8f6f4
+// (unit scales): a K step is 128 values -- 4 taps x 32 channels in conv2, 2
+// taps x 64 channels in conv3 -- so every instruction class (matrix, LDS
+// reads, weight loads) issues a quarter as often per K as with the K = 32
+// instruction, at twice the matrix rate.  conv3's last 64 K values (its
+// ninth tap) use two K = 32 steps.  conv1 is unchanged.
+template <int P, int T, bool K8 = false>
 __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
+  static_assert(!K8 || P == P_FP8, "the K = 128 path is FP8");
   typedef F<P> Fr;
   typedef typename Fr::V V;
   constexpr int EB = Fr::EB;
   constexpr int FRB = kFrameBytes * EB;                 // staged frame bytes
   constexpr int R2 = T * 81, F2 = (R2 + 15) / 16, F2W = (F2 + 3) / 4;
   constexpr int R3 = T * 49, F3 = (R3 + 15) / 16, F3W = (F3 + 3) / 4;
-  typedef Lay<P> L;
+  typedef Lay<P, K8> L;
   // x1 of the round's items; ux holds the round's input frames during conv1
   // and x2 from conv2's epilogue to the end of conv3 (never both at once)
   constexpr int NFR = T > 3 ? T : 3;                    // frames staged at once
@@ -245,6 +261,23 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
     } else {
 #pragma unroll
       for (int j = 0; j < 2; ++j) w[j] = Fr::ldw(W3r, v3, (j * 18 + u - 16) * FB);
+    }
+  };
+  // K8: a channel fragment's weights are 16 rows x K bytes, K128 units of
+  // 32 bytes per lane (then conv3's two K = 32 units of 8 bytes per lane);
+  // step u = 0..3 is conv2, 4..7 conv3
+  const int v2k = half * 2 * 16 * 512 + lane * 32;
+  const int v3k = half * 2 * 16 * 576 + lane * 32;
+  auto wstep8 = [&](int u, v8i (&w)[2]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const bool c2 = u < 4;
+      const __amdgpu_buffer_rsrc_t r = c2 ? W2r : W3r;
+      const int vo = c2 ? v2k : v3k;
+      const int so = c2 ? (j * 16 * 512 + u * 2048) : (j * 16 * 576 + (u - 4) * 2048);
+      const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+      const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so + 16, 0);
+      w[j] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
     }
   };
   unsigned char* X3 = reinterpret_cast<unsigned char*>(a.x3);
@@ -359,6 +392,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
     V wr[kRing][2];      // conv2 / conv3 weight ring (its first kD steps load during conv1)
+    v8i wr8[kRing8][2];  // the same for K8 (kD8 steps ahead)
     lds_barrier();       // the round's frames are staged
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
@@ -412,8 +446,13 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       // vector-memory path (8 wavefronts x 2 KB per step), which conv1 does
       // not otherwise use, so spread out they overlap conv1's work.
       auto ring_part = [&](int j) {
+        if constexpr (K8) {
 #pragma unroll
-        for (int u = j * kD / T; u < (j + 1) * kD / T; ++u) wstep(u, wr[u % kRing]);
+          for (int u = j * kD8 / T; u < (j + 1) * kD8 / T; ++u) wstep8(u, wr8[u % kRing8]);
+        } else {
+#pragma unroll
+          for (int u = j * kD / T; u < (j + 1) * kD / T; ++u) wstep(u, wr[u % kRing]);
+        }
         __builtin_amdgcn_sched_barrier(0);
       };
       reads(0);
@@ -449,6 +488,168 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       }
     }
 
+    if constexpr (K8) {
+    v8i wcur[2], wnxt[2];
+    // ---- conv2 and conv3 on the K = 128 instruction ----
+    // conv2 step s (s = 0..3): lane group g holds tap (kh = s, kw = g), all
+    // 32 channels; conv3 step s (s = 0..3): tap 2s + g/2, channels
+    // 32 (g & 1) .. +31; then conv3's ninth tap as two K = 32 steps.
+    {
+      const int rows2 = nt * 81;
+      f32x4 acc[F2W][2];
+      int base[F2W];
+      bool ok[F2W];
+#pragma unroll
+      for (int i = 0; i < F2W; ++i) {
+        const int r = (fq + 4 * i) * 16 + r16;
+        ok[i] = r < rows2;
+        const int rr = ok[i] ? r : 0;
+        const int t = rr / 81, p = rr % 81;
+        base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P;
+        acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      auto koff2 = [&](int st) {   // this lane's tap (kh = st, kw = g)
+        return ((st & 1) * 2 + (g & 1)) * L::X1PH + ((st >> 1) * 10 + (g >> 1)) * L::X1P;
+      };
+      auto ld32 = [](const unsigned char* q) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
+        return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      };
+      // The K = 128 steps run as a loop (not unrolled, so that the compiler
+      // cannot hoist loads across steps and run out of registers), with the
+      // weight operands rotating through three register sets: the step's,
+      // the next one's, and the one requested kD8 = 2 steps ahead.
+      wcur[0] = wr8[0][0]; wcur[1] = wr8[0][1];
+      wnxt[0] = wr8[1][0]; wnxt[1] = wr8[1][1];
+#pragma unroll 1
+      for (int st = 0; st < 4; ++st) {
+        v8i wfut[2];
+        wstep8(st + 2, wfut);                     // steps 2..5: conv2's last two, conv3's first two
+        const int ko = koff2(st);
+        v8i pv[2];
+        pv[0] = ld32(&x1[base[0] + ko]);
+#pragma unroll
+        for (int i = 0; i < F2W; ++i) {
+          if (i + 1 < F2W) pv[(i + 1) & 1] = ld32(&x1[base[i + 1] + ko]);   // clamped rows
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wcur[j], pv[i & 1], acc[i][j],
+                                                                          0, 0, 0, 127, 0, 127);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          wcur[j] = wnxt[j];
+          wnxt[j] = wfut[j];
+        }
+      }
+      const float sc = a.acc_scale[1], o8 = a.out_s8[1];
+      float bb[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[0][32 * half + 8 * g + 4 * j + q];   // paired rows
+#pragma unroll
+      for (int i = 0; i < F2W; ++i) {
+        if (!ok[i]) continue;
+        const int r = (fq + 4 * i) * 16 + r16;
+        const int t = r / 81, p = r % 81;
+        typename Fr::PK pk[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          pk[j] = Fr::pk4(fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f), fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f),
+                          fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f), fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+        Fr::st8(&ux[L::x2(t, p, 32 * half + 8 * g)], pk[0], pk[1]);
+      }
+    }
+    lds_barrier();
+    {
+      const int rows3 = nt * 49;
+      f32x4 acc[F3W][2];
+      int base[F3W], pt[F3W];
+      bool ok[F3W];
+#pragma unroll
+      for (int i = 0; i < F3W; ++i) {
+        const int r = (fq + 4 * i) * 16 + r16;
+        ok[i] = r < rows3;
+        const int rr = ok[i] ? r : 0;
+        const int p = rr % 49;
+        pt[i] = rr / 49;
+        base[i] = pt[i] * L::X2T + ((p / 7) * 9 + (p % 7)) * L::X2P;
+        acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      auto koff3 = [&](int st) {   // this lane's tap 2 st + g/2, channels 32 (g & 1)
+        const int kk = 2 * st + (g >> 1);
+        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (g & 1);
+      };
+      auto ld32 = [](const unsigned char* q) {
+        const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
+        const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
+        return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      };
+      // the ninth tap's weights (two K = 32 units of 8 bytes per lane)
+      V wt[2][2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          wt[t][j] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(
+                                               W3r, half * 2 * 16 * 576 + lane * 8, j * 16 * 576 + 4 * 2048 + t * 512,
+                                               0));
+#pragma unroll 1
+      for (int st = 0; st < 4; ++st) {
+        v8i wfut[2];
+        if (st < 2) wstep8(st + 6, wfut);         // steps 6, 7 (conv3's last two)
+        const int ko = koff3(st);
+        v8i pv[2];
+        pv[0] = ld32(&ux[base[0] + ko]);
+#pragma unroll
+        for (int i = 0; i < F3W; ++i) {
+          if (i + 1 < F3W) pv[(i + 1) & 1] = ld32(&ux[base[i + 1] + ko]);   // clamped rows
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wcur[j], pv[i & 1], acc[i][j],
+                                                                          0, 0, 0, 127, 0, 127);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          wcur[j] = wnxt[j];
+          wnxt[j] = wfut[j];
+        }
+      }
+      // tap 8 (kh = 2, kw = 2): K = 32 steps t = 0, 1 over channels 32t + 8g .. +7
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int ko = (2 * 9 + 2) * L::X2P + 32 * t + 8 * g;
+#pragma unroll
+        for (int i = 0; i < F3W; ++i) {
+          const V pvt = Fr::ld(&ux[base[i] + ko]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = Fr::mma(wt[t][j], pvt, acc[i][j]);
+        }
+      }
+      const float sc = a.acc_scale[2], o8 = a.out_s8[2];
+      float bb[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[j][q] = sbias[1][32 * half + 8 * g + 4 * j + q];   // permuted rows
+      const long long item_first = i0 + r0;
+#pragma unroll
+      for (int i = 0; i < F3W; ++i) {
+        if (!ok[i]) continue;
+        const int r = (fq + 4 * i) * 16 + r16;
+        const long long item = item_first + pt[i];
+        const int px = r - pt[i] * 49;
+        typename Fr::PK pk[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          pk[j] = Fr::pk4(fmaxf(acc[i][j][0] * sc + bb[j][0], 0.f), fmaxf(acc[i][j][1] * sc + bb[j][1], 0.f),
+                          fmaxf(acc[i][j][2] * sc + bb[j][2], 0.f), fmaxf(acc[i][j][3] * sc + bb[j][3], 0.f), o8);
+        Fr::st8(X3 + fc1_tiled_offset(item, (px * 64 + 32 * half + 8 * g) * EB, EB), pk[0], pk[1]);
+      }
+    }
+    } else {
     // ---- conv2 (x1 -> x2) and conv3 (x2 -> x3) ----
     // The K steps of both layers form one sequence u = 0..33 (conv2 steps
     // 0..15, conv3 steps 16..33).  Weight fragments stream from L2 kD steps
@@ -570,6 +771,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         Fr::st8(X3 + fc1_tiled_offset(item, (px * 64 + 32 * half + 8 * g) * EB, EB), pk[0], pk[1]);
       }
     }
+    }
     lds_barrier();       // conv3's reads of x2 are done: ux takes the next frames
     if (!last) {
 #pragma unroll
@@ -606,7 +808,44 @@ __global__ void fragment_major_kernel(const unsigned char* __restrict__ src, uns
   for (int b = 0; b < 8 * eb; ++b) dp[b] = sp[b];
 }
 
+// Fragment-major copy for the FP8 K = 128 instruction: per channel
+// fragment cf, K128 units (s, lane) of 32 bytes -- W[row][128s + 32(lane/16)
+// .. +31] -- for s < K / 128, then K = 32 units (t, lane) of 8 bytes for the
+// remaining K % 128 values -- W[row][128 (K/128) + 32t + 8(lane/16) .. +7];
+// rows paired as in fragment_major_kernel.  A fragment's 16 rows x K bytes
+// stay one contiguous block.
+__global__ void fragment_major_k128_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                                           int N, int K) {
+  const int NS = K / 128, NT = (K % 128) / 32;
+  const long long units = (long long)(N / 16) * (NS + NT) * 64;
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= units) return;
+  const int lane = (int)(u % 64), su = (int)((u / 64) % (NS + NT)), cf = (int)(u / 64 / (NS + NT));
+  const int l = lane % 16, g = lane / 16;
+  const int row = 32 * (cf / 2) + 8 * (l / 4) + 4 * (cf % 2) + l % 4;
+  const unsigned char* sp;
+  unsigned char* dp = dst + (long long)cf * 16 * K;
+  int nb;
+  if (su < NS) {
+    sp = src + (long long)row * K + 128 * su + 32 * g;
+    dp += ((long long)su * 64 + lane) * 32;
+    nb = 32;
+  } else {
+    const int t = su - NS;
+    sp = src + (long long)row * K + 128 * NS + 32 * t + 8 * g;
+    dp += (long long)NS * 64 * 32 + ((long long)t * 64 + lane) * 8;
+    nb = 8;
+  }
+  for (int b = 0; b < nb; ++b) dp[b] = sp[b];
+}
+
 }  // namespace
+
+void launch_fragment_major_k128(const void* src, void* dst, int N, int K, hipStream_t s) {
+  const long long units = (long long)(N / 16) * (K / 128 + (K % 128) / 32) * 64;
+  hipLaunchKernelGGL(fragment_major_k128_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), N, K);
+}
 
 void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, bool pair8, hipStream_t s) {
   const long long units = (long long)(N / 16) * (K / 32) * 64;
@@ -615,14 +854,20 @@ void launch_fragment_major(const void* src, void* dst, int N, int K, int eb, boo
                      pair8 ? 1 : 0);
 }
 
-void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups, hipStream_t s) {
+void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups, hipStream_t s, bool k8) {
   if (n_groups <= 0) return;
   typedef void (*Kern)(FusedConvArgs);
-  // BF16 at T = 4 exceeds the LDS of one CU: T <= 3; other values take 3
-  const int Tk = (T == 1 || T == 2 || (T == 4 && prec != P_BF16)) ? T : 3;
+  // BF16 at T = 4 exceeds the LDS of one CU: T <= 3; FP8 takes T <= 4 with
+  // the K = 32 instruction and 3..5 with the K = 128 one; other values take 3
+  k8 = k8 && prec == P_FP8;
+  const int Tk = k8 ? ((T == 4 || T == 5) ? T : 3)
+                    : (T == 1 || T == 2 || (T == 4 && prec != P_BF16)) ? T : 3;
   Kern k;
   if (prec == P_BF16) {
     k = Tk == 1 ? conv_fused_kernel<P_BF16, 1> : Tk == 2 ? conv_fused_kernel<P_BF16, 2> : conv_fused_kernel<P_BF16, 3>;
+  } else if (k8) {
+    k = Tk == 4 ? conv_fused_kernel<P_FP8, 4, true> : Tk == 5 ? conv_fused_kernel<P_FP8, 5, true>
+                                                              : conv_fused_kernel<P_FP8, 3, true>;
   } else {
     k = Tk == 1 ? conv_fused_kernel<P_FP8, 1> : Tk == 2 ? conv_fused_kernel<P_FP8, 2>
         : Tk == 4 ? conv_fused_kernel<P_FP8, 4> : conv_fused_kernel<P_FP8, 3>;
@@ -631,10 +876,10 @@ void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups,
   // each loops over the groups b, b + grid, ...  The slot count of a
   // (device, kernel) pair is queried once and cached.
   constexpr int kDevs = 64;
-  static std::atomic<int> slot_cache[kDevs][2][5];
+  static std::atomic<int> slot_cache[kDevs][3][6];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
-  std::atomic<int>* cached = dev < kDevs ? &slot_cache[dev][prec == P_BF16 ? 0 : 1][Tk] : nullptr;
+  std::atomic<int>* cached = dev < kDevs ? &slot_cache[dev][prec == P_BF16 ? 0 : k8 ? 2 : 1][Tk] : nullptr;
   int slots = cached ? cached->load(std::memory_order_relaxed) : 0;
   if (slots <= 0) {
     int ncu = 0, per_cu = 0;

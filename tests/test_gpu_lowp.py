@@ -89,11 +89,15 @@ def sibling_stacks(world, seed, A, n_parents):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("prec", ["BF16", "FP8"])
-def test_sibling_groups_match_emulation(lib, prec):
+@pytest.mark.parametrize("prec,k128", [("BF16", 0), ("FP8", 1), ("FP8", 0)])
+def test_sibling_groups_match_emulation(lib, prec, k128):
+    """The fused kernel on sibling groups against the emulation; FP8 with
+    conv2 / conv3 on the K = 128 instruction (the default) and the K = 32
+    one, in rounds of 3 and 4 stacks."""
     ctx, world = make_ctx(lib, 1003)
     try:
         ctx.set_precision(getattr(lib, prec))
+        ctx.set_tuning(lib.TUNE_FP8_K128, k128)
         ascale = ctx.get_fp8_scales()
         rels = []
         for A, npar in ((18, 3), (6, 4), (4, 4)):
@@ -101,8 +105,12 @@ def test_sibling_groups_match_emulation(lib, prec):
             got = ctx.debug_qnet_siblings(x, 18, A)
             want = Q.qvalues_lowp(x, world.w64, 18, prec.lower(), ascale=ascale)
             rels.append(np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1))
-            # the grouping never changes a stack's arithmetic
+            # the grouping never changes a stack's arithmetic, nor the round size
             np.testing.assert_array_equal(got, ctx.debug_qnet_siblings(x, 18, 1))
+            if prec == "FP8":
+                ctx.set_tuning(lib.TUNE_FUSED_ROUND, 4)
+                np.testing.assert_array_equal(got, ctx.debug_qnet_siblings(x, 18, A))
+                ctx.set_tuning(lib.TUNE_FUSED_ROUND, 3)
         check_bars(np.concatenate(rels), prec, "sibling-group stacks vs emulation")
     finally:
         ctx.close()
