@@ -186,12 +186,32 @@ bcts_status bcts_search_batch_device_noalloc(bcts_ctx* ctx, int32_t n_roots, con
 
 /* Capture the device search of one batch shape into a HIP graph and replay
  * it `replays` times (buffers as in bcts_search_batch_device, stream NULL =
- * context stream).  Results of every replay equal the eager search.        */
+ * context stream), synchronising at the end; the graph is captured for this
+ * call and released after it.  Results of every replay equal the eager
+ * search.                                                                  */
 bcts_status bcts_search_batch_graph(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos,
                                     const uint8_t* d_stacks, const int32_t* depth,
                                     const int32_t* A, float gamma, bcts_correction corr,
                                     int32_t* d_out_action, float* d_out_q, int32_t replays,
                                     void* hip_stream);
+
+/* A reusable captured search: the launch sequence of one batch shape (Alg. 1
+ * for every root, then the correction) as an instantiated HIP graph on fixed
+ * device input and output buffers, with its own work memory.  Create it
+ * once (device buffers as in bcts_search_batch_device; they must stay
+ * allocated while the graph exists, and a replay reads whatever they hold
+ * then), then launch it any number of times on any stream without planning,
+ * allocation or host synchronisation; results equal the eager search of
+ * the buffers' contents at replay time.  While a graph exists the calls
+ * that change the model or its settings (those refused while serving)
+ * return BCTS_E_STATE.  bcts_graph_destroy waits for the device and frees
+ * the graph's memory; it must be called before bcts_destroy.               */
+typedef struct bcts_graph bcts_graph;
+bcts_status bcts_graph_create(bcts_ctx* ctx, int32_t n_roots, const int32_t* d_pos, const uint8_t* d_stacks,
+                              const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                              int32_t* d_out_action, float* d_out_q, void* hip_stream, bcts_graph** out);
+bcts_status bcts_graph_launch(bcts_graph* graph, int32_t replays, void* hip_stream);
+void bcts_graph_destroy(bcts_graph* graph);
 
 /* ---- tuning -------------------------------------------------------------- */
 /* Q-network execution choices (none changes results beyond the operand

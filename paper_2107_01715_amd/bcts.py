@@ -42,7 +42,8 @@ EXPORTS = (
     "bcts_set_tuning", "bcts_get_tuning", "bcts_autotune",
     "bcts_set_mlp", "bcts_mlp_search", "bcts_mlp_search_device", "bcts_set_beam",
     "bcts_debug_qnet_siblings", "bcts_search_batch_device_noalloc", "bcts_serve_stats",
-    "bcts_debug_fail_launches", "bcts_debug_expand_batch",
+    "bcts_debug_fail_launches", "bcts_debug_expand_batch", "bcts_graph_create", "bcts_graph_launch",
+    "bcts_graph_destroy",
 )
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32, TUNE_MLP_CROSSOVER = 0, 1, 2, 3, 4, 5
 TUNE_FP8_K128 = 6
@@ -93,6 +94,10 @@ _progress = _sig("bcts_progress", c_int32, _P, POINTER(c_int32))
 _poll = _sig("bcts_poll", c_int32, _P, c_uint64, POINTER(c_int32), _P, POINTER(c_double))
 _serve_config = _sig("bcts_serve_config", c_int32, _P, c_int32, c_int32)
 _serve_stats = _sig("bcts_serve_stats", c_int32, _P, _P)
+_graph_create = _sig("bcts_graph_create", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, CorrectionC, _P, _P, _P,
+                     POINTER(c_void_p))
+_graph_launch = _sig("bcts_graph_launch", c_int32, _P, c_int32, _P)
+_graph_destroy = _sig("bcts_graph_destroy", None, _P)
 _debug_expand_batch = _sig("bcts_debug_expand_batch", c_int32, _P, c_int32, _P, _P, _P, _P, c_float, _P, _P, _P, _P,
                            _P, _P, _P, _P)
 _debug_fail_launches = _sig("bcts_debug_fail_launches", c_int32, _P, c_int32)
@@ -248,6 +253,35 @@ def bcts_search_batch_graph(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, 
     _check(ctx, _search_batch_graph(ctx, pos_t.shape[0], _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8),
                                     _ptr(d), _ptr(a), gamma, corr, _dev(act_t, torch.int32, n),
                                     _dev(q_t, torch.float32, n * MAX_A), replays, s))
+
+
+class Graph:
+    """A captured search (bcts_graph_create); launch() replays it."""
+
+    def __init__(self, ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, stream=None):
+        n = pos_t.shape[0]
+        d = _arr(depth, np.int32)
+        a = _arr(A, np.int32)
+        s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
+        h = c_void_p()
+        _check(ctx, _graph_create(ctx, n, _dev(pos_t, torch.int32), _dev(stacks_t, torch.uint8), _ptr(d), _ptr(a),
+                                  gamma, corr, _dev(act_t, torch.int32, n), _dev(q_t, torch.float32, n * MAX_A), s,
+                                  byref(h)))
+        self.ctx, self.h = ctx, h
+        self._keep = (pos_t, stacks_t, act_t, q_t)      # the buffers the graph reads and writes
+
+    def launch(self, replays: int = 1, stream=None):
+        s = c_void_p(stream.cuda_stream) if stream is not None else c_void_p(torch.cuda.current_stream().cuda_stream)
+        _check(self.ctx, _graph_launch(self.h, replays, s))
+
+    def close(self):
+        if self.h:
+            _graph_destroy(self.h)
+            self.h = None
+
+
+def bcts_graph_create(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, stream=None) -> Graph:
+    return Graph(ctx, pos_t, stacks_t, depth, A, gamma, corr, act_t, q_t, stream)
 
 
 def bcts_submit(ctx, pos, stack, depth: int, A: int, gamma: float, corr: CorrectionC) -> int:

@@ -105,6 +105,9 @@ struct bcts_ctx {
   struct ServeEngine* serve = nullptr;
   // launches still to fail on purpose (bcts_debug_fail_launches)
   int inject_fail = 0;
+  // captured search graphs alive (bcts_graph_create): they read the
+  // weights, so the calls that replace them refuse while any exists
+  int live_graphs = 0;
   // learned forward-model world (device weights, and a host copy for the
   // host levels of a search that starts on the CPU)
   void* mlp_mem = nullptr;
@@ -899,6 +902,8 @@ struct ServeEngine {
 // requests and admitted cohorts (finished results waiting for bcts_poll do
 // not count).  The calls that change that state refuse while it exists.
 static bcts_status refuse_if_serving(bcts_ctx* c, const char* what) {
+  if (c->live_graphs > 0)
+    return fail(c, BCTS_E_STATE, "%s: %d captured search graph(s) still exist", what, c->live_graphs);
   if (!c->serve) return BCTS_OK;
   bcts_status st = c->serve->retire();
   if (st != BCTS_OK) return st;
@@ -1316,46 +1321,124 @@ bcts_status bcts_search_batch_device_noalloc(bcts_ctx* c, int32_t n, const int32
   return BCTS_OK;
 }
 
-bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
-                                    const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
-                                    int32_t* d_act, float* d_q, int32_t replays, void* hip_stream) {
+}  // extern "C"
+
+// A captured search: its own arena (so later calls may grow or free the
+// context's), the plan's tables uploaded once, and the instantiated graph
+// of the launch sequence on fixed input and output pointers.
+struct bcts_graph {
+  bcts_ctx* c = nullptr;
+  char* arena = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long long leaves = 0;
+};
+
+extern "C" {
+
+bcts_status bcts_graph_create(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
+                              const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                              int32_t* d_act, float* d_q, void* hip_stream, bcts_graph** out) {
   bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
+  if (!out) return fail(c, BCTS_E_INVAL, "NULL graph handle");
+  *out = nullptr;
   if ((st = validate_common(c, n, gamma, corr)) != BCTS_OK) return st;
   if (!d_pos || !d_stacks || !d_act || !d_q || !depth || !A) return fail(c, BCTS_E_INVAL, "NULL buffer");
-  if (replays < 1) return fail(c, BCTS_E_INVAL, "replays must be >= 1");
   for (int r = 0; r < n; ++r)
     if ((st = validate_shape(c, A[r], depth[r], corr)) != BCTS_OK) return st;
   HIPCHECK(c, hipSetDevice(c->device));
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
   Plan p;
   plan_search(c, p, n, depth, A, gamma, corr, kMaxA, false);
-  if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
-  if ((st = upload_tables(c, p, s)) != BCTS_OK) return st;
-  HIPCHECK(c, hipStreamSynchronize(s));
-  c->arena_pending = false;
+  const size_t used = c->wbytes + c->arena_bytes;
+  if (p.total + used > c->budget)
+    return fail(c, BCTS_E_NOMEM, "graph needs %zu bytes of device memory; the budget leaves %zu", p.total,
+                c->budget > used ? c->budget - used : 0);
+  bcts_graph* g = new bcts_graph();
+  g->c = c;
+  for (int r = 0; r < n; ++r) {
+    long long lv = 1;
+    for (int k = 0; k < depth[r]; ++k) lv *= A[r];
+    g->leaves += lv;
+  }
+  auto undo = [&](bcts_status e) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->arena) (void)hipFree(g->arena);
+    delete g;
+    return e;
+  };
+  if (hipMalloc((void**)&g->arena, p.total) != hipSuccess) {
+    (void)hipGetLastError();
+    g->arena = nullptr;
+    return undo(fail(c, BCTS_E_NOMEM, "hipMalloc(%zu) for the graph's arena failed", p.total));
+  }
+  // tables: staged through host memory, copied before any replay can run
+  std::vector<char> h(p.table_bytes);
+  if ((st = upload_tables_at(c, p, g->arena, h.data(), s)) != BCTS_OK) return undo(st);
+  if (hipStreamSynchronize(s) != hipSuccess) return undo(fail(c, BCTS_E_HIP, "table upload failed"));
   hipStream_t cap;
-  HIPCHECK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+    return undo(fail(c, BCTS_E_HIP, "hipStreamCreate failed"));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = enqueue_search(c, p, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, cap, false);
-    hipError_t e2 = hipStreamEndCapture(cap, &graph);
-    if (st == BCTS_OK && e2 != hipSuccess) e = e2;
+    st = enqueue_search_at(c, p, g->arena, d_pos, d_stacks, gamma, corr.enabled ? corr.scale : 0.f, d_act, d_q, cap,
+                           false);
+    const hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
+    if (e == hipSuccess) e = e2;
   }
-  if (e == hipSuccess && st == BCTS_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e == hipSuccess && st == BCTS_OK) {
-    if (c->timing) e = hipEventRecord(c->ev[0], s);
-    for (int i = 0; i < replays && e == hipSuccess; ++i) e = hipGraphLaunch(exec, s);
-    if (c->timing && e == hipSuccess) e = hipEventRecord(c->ev[3], s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-  }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  if (e == hipSuccess && st == BCTS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cap);
+  if (st != BCTS_OK) return undo(st);
+  if (e != hipSuccess) return undo(fail(c, BCTS_E_HIP, "graph capture failed: %s", hipGetErrorString(e)));
+  ++c->live_graphs;
+  *out = g;
+  return BCTS_OK;
+}
+
+bcts_status bcts_graph_launch(bcts_graph* g, int32_t replays, void* hip_stream) {
+  if (!g) return BCTS_E_INVAL;
+  bcts_ctx* c = g->c;
+  bcts_status st = check_usable(c);
   if (st != BCTS_OK) return st;
-  if (e != hipSuccess) return fail(c, BCTS_E_HIP, "graph capture/replay failed: %s", hipGetErrorString(e));
+  if (replays < 1) return fail(c, BCTS_E_INVAL, "replays must be >= 1");
+  if ((st = launch_gate(c)) != BCTS_OK) return st;
+  HIPCHECK(c, hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  for (int i = 0; i < replays; ++i) HIPCHECK(c, hipGraphLaunch(g->exec, s));
+  return BCTS_OK;
+}
+
+void bcts_graph_destroy(bcts_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->c->device);
+  (void)hipDeviceSynchronize();           // replays on any stream have finished
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->arena) (void)hipFree(g->arena);
+  --g->c->live_graphs;
+  delete g;
+}
+
+bcts_status bcts_search_batch_graph(bcts_ctx* c, int32_t n, const int32_t* d_pos, const uint8_t* d_stacks,
+                                    const int32_t* depth, const int32_t* A, float gamma, bcts_correction corr,
+                                    int32_t* d_act, float* d_q, int32_t replays, void* hip_stream) {
+  bcts_status st = check_usable(c);
+  if (st != BCTS_OK) return st;
+  if (replays < 1) return fail(c, BCTS_E_INVAL, "replays must be >= 1");
+  bcts_graph* g = nullptr;
+  if ((st = bcts_graph_create(c, n, d_pos, d_stacks, depth, A, gamma, corr, d_act, d_q, hip_stream, &g)) != BCTS_OK)
+    return st;
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+  hipError_t e = hipSuccess;
+  if (c->timing) e = hipEventRecord(c->ev[0], s);
+  if (e == hipSuccess) st = bcts_graph_launch(g, replays, hip_stream);
+  if (st == BCTS_OK && c->timing && e == hipSuccess) e = hipEventRecord(c->ev[3], s);
+  if (st == BCTS_OK && e == hipSuccess) e = hipStreamSynchronize(s);
+  bcts_graph_destroy(g);
+  if (st != BCTS_OK) return st;
+  if (e != hipSuccess) return fail(c, BCTS_E_HIP, "graph replay failed: %s", hipGetErrorString(e));
   if (c->timing) {
     float ms = 0.f;
     HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));

@@ -98,3 +98,44 @@ def test_mixed_batch_as_one_graph(lib):
         assert rel < 2e-2, (r, rel)
     ctx.set_precision(lib.FP32)
     ctx.close()
+
+
+def test_graph_handle_is_reusable(lib):
+    """bcts_graph_create captures one batch shape once; launches replay it on
+    whatever the input buffers hold, with eager searches in between, and
+    equal the eager search bit for bit; the model's settings are refused
+    while the graph exists."""
+    import torch
+    ctx, _ = make(lib, 1004)
+    g = None
+    try:
+        ctx.set_precision(lib.BF16)
+        n = 12
+        A, d = W.mixed_shapes(1008, n, (4, 6, 18), (1, 2, 3))
+        corr = lib.correction(True, 1.0)
+        dev = torch.device("cuda:0")
+        pos_a, st_a = W.roots(1008, n)
+        pos_b, st_b = W.roots(1009, n)
+        pt = torch.from_numpy(pos_a).to(dev)
+        stt = torch.from_numpy(st_a).to(dev)
+        at = torch.zeros(n, dtype=torch.int32, device=dev)
+        qt = torch.zeros(n, 18, dtype=torch.float32, device=dev)
+        g = ctx.graph_create(pt, stt, d, A, GAMMA, corr, at, qt)
+        with pytest.raises(lib.BctsError) as e:
+            ctx.set_precision(lib.FP32)
+        assert e.value.status == lib.E_STATE
+        for pos, st in ((pos_a, st_a), (pos_b, st_b), (pos_a, st_a)):
+            pt.copy_(torch.from_numpy(pos))
+            stt.copy_(torch.from_numpy(st))
+            a_ref, q_ref = ctx.search_batch(pos, st, d, A, GAMMA, corr)     # eager work in between
+            at.fill_(-1)
+            g.launch(2)
+            torch.cuda.synchronize()
+            assert np.array_equal(at.cpu().numpy(), a_ref)
+            assert np.array_equal(qt.cpu().numpy(), q_ref)
+        g.close()
+        ctx.set_precision(lib.FP32)                       # allowed again
+    finally:
+        if g is not None:
+            g.close()
+        ctx.close()
