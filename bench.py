@@ -114,30 +114,45 @@ def agreement(act, q, ref):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "conv_fused_bf16_256roots_A18_d3_traffic.md")
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "conv_fused_fc1_bf16_fp8_256roots_A18_d3_sq_counters.md")
 
 
-def measured_traffic(kernel, precision, fused, tuned):
-    """HBM bytes per stack of the dominant kernel from the committed counter
-    summary, only for the kernel and round size it was measured on and while
-    the kernel's source is unchanged since (else None).  The per-stack figure
-    does not depend on how the stacks are chunked into launches (measured at
-    two chunk sizes)."""
+def _profile_value(path, pattern):
+    """A figure from a committed counter summary, only while the fused
+    kernel's source (and the header that fixes its output layout) is the one
+    it was measured on (else None)."""
     import hashlib
     import re
-    if kernel != "conv_fused" or precision != "bf16" or not fused or tuned.get("round") != 3:
-        return None
     csrc = os.path.join(ROOT, "paper_2107_01715_amd", "csrc")
     try:
-        text = open(TRAFFIC_PROFILE).read()
-        # the kernel and the header that fixes its output layout
+        text = open(path).read()
         src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("qnet_fused.hip", "bcts_internal.h"))
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_stack:\s*([0-9.]+)", text)
+    m = re.search(pattern, text)
     h = re.search(r"source_sha256 qnet_fused.hip\+bcts_internal.h:\s*([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != hashlib.sha256(src).hexdigest():
         return None
     return float(m.group(1))
+
+
+def measured_traffic(kernel, precision, fused, tuned):
+    """HBM bytes per stack of the dominant kernel (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), for the kernel and round size it was measured on.  The
+    per-stack figure does not depend on how the stacks are chunked."""
+    if kernel != "conv_fused" or precision != "bf16" or not fused or tuned.get("round") != 3:
+        return None
+    return _profile_value(TRAFFIC_PROFILE, r"traffic_bytes_per_stack:\s*([0-9.]+)")
+
+
+def measured_executed_flops(kernel, precision, fused, tuned):
+    """Matrix-core FLOP per stack the fused kernel executes (counter
+    SQ_INSTS_VALU_MFMA_MOPS_* x 512), for the launch shape it was measured on."""
+    if kernel != "conv_fused" or precision not in ("bf16", "fp8") or not fused or tuned.get("round") != 3:
+        return None
+    if precision == "fp8" and not tuned.get("fp8_k128"):
+        return None
+    return _profile_value(COUNTER_PROFILE, r"executed_flop_per_stack %s:\s*([0-9.]+)" % precision)
 
 
 def _setup(seed, n_roots, budget=0):
@@ -708,9 +723,12 @@ def main():
         if prec != "fp32":
             accuracy[prec]["vs_fp32_gpu"] = agreement(a_, q_, gpu32_ref)
 
-    # per-kernel roofline of the headline precision
+    # per-kernel roofline of the headline precision; on the fused path the
+    # root and depth-1 evaluations of the correction run in FP32 beside the
+    # chunks, so the chunks' kernels see the leaves only
     n_items = kern[16]
     fused = kern[18] > 0.5
+    main_items = n_items - N_ROOTS * (A + 1) if fused and kern[19] > 0 else n_items
     names = ("conv_fused", None, None, "fc1", "fc2") if fused else ("conv1", "conv2", "conv3", "fc1", "fc2")
     flops_of = dict(LAYER_FLOPS)
     flops_of["conv_fused"] = LAYER_FLOPS["conv1"] + LAYER_FLOPS["conv2"] + LAYER_FLOPS["conv3"]
@@ -720,7 +738,7 @@ def main():
             continue
         ms = kern[4 + i]
         launches = kern[9]
-        flops = flops_of[name] * n_items
+        flops = flops_of[name] * main_items
         kernels[name] = {"ms_per_step": ms, "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                          "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else None,
                          "algorithmic_flop_per_stack": flops_of[name]}
@@ -732,12 +750,20 @@ def main():
     exp_gbs = exp_nodes * EXPAND_BYTES_PER_NODE / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else None
     qnet_tflops = leaves * sum(LAYER_FLOPS.values()) / (kern[1] * 1e-3) / 1e12 if kern[1] > 0 else None
     per_stack = measured_traffic(dom, args.precision, fused, tuned)
-    traffic = per_stack * n_items / max(kern[9], 1) if per_stack is not None else None
+    traffic = per_stack * main_items / max(kern[9], 1) if per_stack is not None else None
+    ex_stack = measured_executed_flops(dom, args.precision, fused, tuned)
+    ex_tflops = (ex_stack * main_items / (kernels[dom]["ms_per_step"] * 1e-3) / 1e12
+                 if ex_stack is not None and kernels[dom]["ms_per_step"] > 0 else None)
     roofline = {"bound": "mfma", "kernel": LAYER_KERNEL[dom].replace("P", args.precision).replace("T", str(tuned.get("round", ""))),
                 "layer": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "flop_per_launch": flops_of[dom] * n_items / max(kern[9], 1),
+                "flop_per_launch": flops_of[dom] * main_items / max(kern[9], 1),
                 "avg_launch_ms": kernels[dom]["avg_launch_ms"], "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "achieved_is": "algorithmic FLOP (the three plain convolutions per stack) / HIP-event kernel time",
+                "executed": ({"achieved": ex_tflops, "frac": ex_tflops / peak, "flop_per_stack": ex_stack,
+                              "what": "matrix-core FLOP the kernel executes (rocprofv3 SQ_INSTS_VALU_MFMA_MOPS x 512: "
+                                      "conv1 shared by siblings, padded rows) / the same kernel time"}
+                             if ex_tflops is not None else None)}
 
     lat = np.array(per_step) if per_step else np.array([ms_step])
     out = {
