@@ -55,7 +55,7 @@ constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
 constexpr int kD8 = 2;                 // K8 weight lookahead in K = 128 steps (requested during conv1)
-constexpr int kRing8 = kD8;
+constexpr int kRing8 = kD8 + 1;         // K8 weight ring: step u in slot u % kRing8
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -207,6 +207,18 @@ template <int P, bool K8 = false> struct Lay {
 // reads, weight loads) issues a quarter as often per K as with the K = 32
 // instruction, at twice the matrix rate.  conv3's last 64 K values (its
 // ninth tap) use two K = 32 steps.  conv1 is unchanged.
+// Makes the accumulators' current values materialise here (an empty asm
+// that reads and rewrites them): without it the compiler sinks a fragment's
+// whole chain of matrix instructions into its conditional epilogue, which
+// keeps every step's operands live at once and spills.
+template <int N>
+__device__ __forceinline__ void pin_acc(f32x4 (&acc)[N][2]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) asm volatile("" : "+v"(acc[i][j]));
+}
+
 template <int P, int T, bool K8 = false>
 __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
   static_assert(!K8 || P == P_FP8, "the K = 128 path is FP8");
@@ -489,7 +501,6 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
     }
 
     if constexpr (K8) {
-    v8i wcur[2], wnxt[2];
     // ---- conv2 and conv3 on the K = 128 instruction ----
     // conv2 step s (s = 0..3): lane group g holds tap (kh = s, kw = g), all
     // 32 channels; conv3 step s (s = 0..3): tap 2s + g/2, channels
@@ -508,24 +519,29 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
+      // (gp: the lane group, re-derived here so that the compiler keeps the
+      // per-step offsets inside the round instead of holding all of them in
+      // registers across it)
+      int gp = g;
+      asm volatile("" : "+v"(gp));
       auto koff2 = [&](int st) {   // this lane's tap (kh = st, kw = g)
-        return ((st & 1) * 2 + (g & 1)) * L::X1PH + ((st >> 1) * 10 + (g >> 1)) * L::X1P;
+        return ((st & 1) * 2 + (gp & 1)) * L::X1PH + ((st >> 1) * 10 + (gp >> 1)) * L::X1P;
       };
       auto ld32 = [](const unsigned char* q) {
         const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
         const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
         return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       };
-      // The K = 128 steps run as a loop (not unrolled, so that the compiler
-      // cannot hoist loads across steps and run out of registers), with the
-      // weight operands rotating through three register sets: the step's,
-      // the next one's, and the one requested kD8 = 2 steps ahead.
-      wcur[0] = wr8[0][0]; wcur[1] = wr8[0][1];
-      wnxt[0] = wr8[1][0]; wnxt[1] = wr8[1][1];
-#pragma unroll 1
+      // Weight step u sits in ring slot u % 3 (the step's, the next one's and
+      // the one requested kD8 = 2 steps ahead), so the steps rotate by slot
+      // index, not by register copies: a copy of a register still being
+      // loaded makes the wavefront wait for that load, which cut the
+      // lookahead to one step.  A scheduling barrier closes every step, so
+      // the compiler cannot hoist a later step's pixel reads and run out of
+      // registers.
+#pragma unroll
       for (int st = 0; st < 4; ++st) {
-        v8i wfut[2];
-        wstep8(st + 2, wfut);                     // steps 2..5: conv2's last two, conv3's first two
+        wstep8(st + 2, wr8[(st + 2) % kRing8]);   // steps 2..5: conv2's last two, conv3's first two
         const int ko = koff2(st);
         v8i pv[2];
         pv[0] = ld32(&x1[base[0] + ko]);
@@ -534,14 +550,11 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
           if (i + 1 < F2W) pv[(i + 1) & 1] = ld32(&x1[base[i + 1] + ko]);   // clamped rows
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wcur[j], pv[i & 1], acc[i][j],
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wr8[st % kRing8][j], pv[i & 1], acc[i][j],
                                                                           0, 0, 0, 127, 0, 127);
         }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          wcur[j] = wnxt[j];
-          wnxt[j] = wfut[j];
-        }
+        pin_acc(acc);
+        __builtin_amdgcn_sched_barrier(0);
       }
       const float sc = a.acc_scale[1], o8 = a.out_s8[1];
       float bb[2][4];
@@ -578,28 +591,32 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         base[i] = pt[i] * L::X2T + ((p / 7) * 9 + (p % 7)) * L::X2P;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
+      int gp = g;                  // (re-derived in the round, as in conv2)
+      asm volatile("" : "+v"(gp));
       auto koff3 = [&](int st) {   // this lane's tap 2 st + g/2, channels 32 (g & 1)
-        const int kk = 2 * st + (g >> 1);
-        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (g & 1);
+        const int kk = 2 * st + (gp >> 1);
+        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (gp & 1);
       };
       auto ld32 = [](const unsigned char* q) {
         const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
         const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
         return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       };
-      // the ninth tap's weights (two K = 32 units of 8 bytes per lane)
+      // the ninth tap's weights (two K = 32 units of 8 bytes per lane),
+      // requested with the last ring step's loads
       V wt[2][2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          wt[t][j] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(
-                                               W3r, half * 2 * 16 * 576 + lane * 8, j * 16 * 576 + 4 * 2048 + t * 512,
-                                               0));
-#pragma unroll 1
       for (int st = 0; st < 4; ++st) {
-        v8i wfut[2];
-        if (st < 2) wstep8(st + 6, wfut);         // steps 6, 7 (conv3's last two)
+        if (st < 2) wstep8(st + 6, wr8[(st + 6) % kRing8]);   // steps 6, 7 (conv3's last two)
+        if (st == 2) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              wt[t][j] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(
+                                                   W3r, half * 2 * 16 * 576 + lane * 8,
+                                                   j * 16 * 576 + 4 * 2048 + t * 512, 0));
+        }
         const int ko = koff3(st);
         v8i pv[2];
         pv[0] = ld32(&ux[base[0] + ko]);
@@ -608,14 +625,11 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
           if (i + 1 < F3W) pv[(i + 1) & 1] = ld32(&ux[base[i + 1] + ko]);   // clamped rows
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wcur[j], pv[i & 1], acc[i][j],
-                                                                          0, 0, 0, 127, 0, 127);
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wr8[(st + 4) % kRing8][j], pv[i & 1],
+                                                                          acc[i][j], 0, 0, 0, 127, 0, 127);
         }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          wcur[j] = wnxt[j];
-          wnxt[j] = wfut[j];
-        }
+        pin_acc(acc);
+        __builtin_amdgcn_sched_barrier(0);
       }
       // tap 8 (kh = 2, kw = 2): K = 32 steps t = 0, 1 over channels 32t + 8g .. +7
 #pragma unroll
