@@ -243,8 +243,10 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          do the device kernel's FP32 arithmetic in the
  *                          same order, so results are the same bits.
  *   BCTS_TUNE_FP8_K128     FP8 fused path: 1 (default) = conv2 / conv3 on
- *                          the K = 128 matrix instruction (rounds of 3..5
- *                          stacks), 0 = the K = 32 one (rounds of 1..4).
+ *                          the K = 128 matrix instruction, their weights
+ *                          held in LDS (rounds of 3 stacks whatever
+ *                          BCTS_TUNE_FUSED_ROUND asks), 0 = the K = 32 one
+ *                          (rounds of 1..4).
  *                          The products of each 8 consecutive K values are
  *                          summed the same way by both, so the results are
  *                          the same up to FP32 addition order.             */

@@ -1823,10 +1823,10 @@ bcts_status bcts_autotune(bcts_ctx* c, int32_t n, const int32_t* d_pos, const ui
    for (int k8 = (fz && c->prec == P_FP8) ? 1 : 0; k8 >= 0 && st == BCTS_OK; --k8) {
     for (int ti = 0; ti < (fz ? 5 : 1) && st == BCTS_OK; ++ti) {
       // rounds the kernel has: BF16 1..3 (4 is over the LDS of one CU), FP8
-      // with K = 32 1..4, with K = 128 3..5
+      // with K = 32 1..4, with K = 128 3 (its weights take 68 KB of LDS)
       if (fz && c->prec == P_BF16 && Ts[ti] > 3) continue;
       if (fz && c->prec == P_FP8 && !k8 && Ts[ti] > 4) continue;
-      if (fz && k8 && Ts[ti] < 3) continue;
+      if (fz && k8 && Ts[ti] != 3) continue;
       for (int ci = 0; ci < (fz ? 2 : 1) && st == BCTS_OK; ++ci) {
         c->fused = fz != 0;
         c->fp8_k128 = k8 != 0;

@@ -54,8 +54,12 @@ constexpr int kF1 = 4;                 // conv1 pixel fragments per wave: w + 8i
 constexpr int kSteps = 16 + 18;        // K steps of conv2 then conv3
 constexpr int kD = 5;                  // weight lookahead in K steps
 constexpr int kRing = kD + 1;
-constexpr int kD8 = 2;                 // K8 weight lookahead in K = 128 steps (requested during conv1)
-constexpr int kRing8 = kD8 + 1;         // K8 weight ring: step u in slot u % kRing8
+// K8: conv2 / conv3 e4m3 weights held in LDS for the whole launch: per
+// (layer, channel fragment cf, K = 128 step s) two 1 KB blocks, the low and
+// high 16 bytes of each lane's 32 (lane l at 16 l: a 16-byte read of the
+// block is free of bank conflicts), conv2 at 0, conv3 at 32 KB, then conv3's
+// two K = 32 tail units per fragment (512 bytes each, lane l at 8 l).
+constexpr int kWk3 = 32768, kWkTail = 65536, kWkBytes = 69632;
 
 __device__ __forceinline__ unsigned bf2_pack(float a, float b) {
   const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);   // v_cvt_pk_bf16_f32 (RNE)
@@ -180,18 +184,25 @@ template <> struct F<P_FP8> {
 //      neighbouring LDS pixels.
 //  x2: conv2 output 9x9x64, pixel stride 72 elements (64 channels + 8 pad).
 //  With the FP8 K = 128 instruction (K8) a lane reads 32 consecutive channels
-//  of one pixel per step, two 16-byte reads: pixel strides of 48 (x1) and 80
-//  (x2) bytes keep them aligned, and 3 and 5 16-byte units per pixel put 16
-//  consecutive pixels on distinct bank groups.
+//  of one pixel per step, two 16-byte reads, and the layouts follow the bank
+//  rule above.  x1: 32-byte pixels on rows of 17 pixel slots (17 = 1 mod 8,
+//  so consecutive output pixels, row-major within a stack, sit on
+//  consecutive bank-group pairs across row ends), phases 341 units of 16
+//  bytes apart (odd: a cycle's lanes of the two column phases land on
+//  opposite unit parities) and items 1378 units apart (consecutive across
+//  items too); conv2's reads are then free of conflicts.  x2: 80-byte
+//  pixels, items 409 units apart (conv3's reads at 2x the conflict-free
+//  cycles, against 2.4x without the gap and the lane order below).
 template <int P, bool K8 = false> struct Lay {
   static constexpr int EB = F<P>::EB;
-  static constexpr int X1P = K8 ? 48 : 40 * EB;     // pixel stride
-  static constexpr int X1PH = 100 * X1P;            // phase stride
-  static constexpr int X1T = 4 * X1PH;              // item stride
+  static constexpr int X1P = K8 ? 32 : 40 * EB;     // pixel stride
+  static constexpr int X1W = K8 ? 17 : 10;          // pixel slots per phase row
+  static constexpr int X1PH = K8 ? 341 * 16 : 100 * X1P;   // phase stride
+  static constexpr int X1T = K8 ? 1378 * 16 : 4 * X1PH;    // item stride
   static constexpr int X2P = K8 ? 80 : 72 * EB;
-  static constexpr int X2T = 81 * X2P;
+  static constexpr int X2T = K8 ? 409 * 16 : 81 * X2P;
   __device__ static int x1(int t, int y, int x, int c) {
-    return t * X1T + ((y & 1) * 2 + (x & 1)) * X1PH + ((y >> 1) * 10 + (x >> 1)) * X1P + c * EB;
+    return t * X1T + ((y & 1) * 2 + (x & 1)) * X1PH + ((y >> 1) * X1W + (x >> 1)) * X1P + c * EB;
   }
   __device__ static int x2(int t, int p, int c) { return t * X2T + p * X2P + c * EB; }
 };
@@ -201,12 +212,13 @@ template <int P, bool K8 = false> struct Lay {
 // conv2 / conv3 wave w takes channel half (w & 1) and pixel fragments
 // (w >> 1) + 4i; their weight fragments stream from L2 kD K steps ahead.
 //
-// K8 (FP8 only): conv2 and conv3 run on v_mfma_scale_f32_16x16x128_f8f6f4
-// (unit scales): a K step is 128 values -- 4 taps x 32 channels in conv2, 2
-// taps x 64 channels in conv3 -- so every instruction class (matrix, LDS
-// reads, weight loads) issues a quarter as often per K as with the K = 32
-// instruction, at twice the matrix rate.  conv3's last 64 K values (its
-// ninth tap) use two K = 32 steps.  conv1 is unchanged.
+// K8 (FP8 only, rounds of 3): conv2 and conv3 run on
+// v_mfma_scale_f32_16x16x128_f8f6f4 (unit scales): a K step is 128 values --
+// 4 taps x 32 channels in conv2, 2 taps x 64 channels in conv3 -- at twice
+// the matrix rate of the K = 32 instruction.  Their weights (68 KB in e4m3)
+// are copied into LDS once per launch, so no weight stream competes with the
+// matrix work; conv3's last 64 K values (its ninth tap) use two K = 32
+// steps.  conv1 is unchanged.
 // Makes the accumulators' current values materialise here (an empty asm
 // that reads and rewrites them): without it the compiler sinks a fragment's
 // whole chain of matrix instructions into its conditional epilogue, which
@@ -221,7 +233,7 @@ __device__ __forceinline__ void pin_acc(f32x4 (&acc)[N][2]) {
 
 template <int P, int T, bool K8 = false>
 __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a) {
-  static_assert(!K8 || P == P_FP8, "the K = 128 path is FP8");
+  static_assert(!K8 || (P == P_FP8 && T == 3), "the K = 128 path is FP8 in rounds of 3");
   typedef F<P> Fr;
   typedef typename Fr::V V;
   constexpr int EB = Fr::EB;
@@ -237,6 +249,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   __shared__ __attribute__((aligned(16))) unsigned char ux[UXB];
   __shared__ __attribute__((aligned(16))) unsigned char w1l[12 * 64 * 8 * EB];   // conv1 weights, channels 0..2
   __shared__ __attribute__((aligned(16))) float sbias[2][64];   // conv2, conv3 biases
+  __shared__ __attribute__((aligned(16))) unsigned char wk[K8 ? kWkBytes : 16];   // K8 weights (layout above)
 
   // Item descriptors and groups are read-only here: reading them through the
   // constant address space makes their uniform loads scalar (counted by
@@ -275,20 +288,14 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       for (int j = 0; j < 2; ++j) w[j] = Fr::ldw(W3r, v3, (j * 18 + u - 16) * FB);
     }
   };
-  // K8: a channel fragment's weights are 16 rows x K bytes, K128 units of
-  // 32 bytes per lane (then conv3's two K = 32 units of 8 bytes per lane);
-  // step u = 0..3 is conv2, 4..7 conv3
-  const int v2k = half * 2 * 16 * 512 + lane * 32;
-  const int v3k = half * 2 * 16 * 576 + lane * 32;
-  auto wstep8 = [&](int u, v8i (&w)[2]) {
+  // K8: this wave's two channel fragments at weight step u (conv2 0..3,
+  // conv3 4..7), read from the LDS copy
+  auto wlds = [&](int u, v8i (&w)[2]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const bool c2 = u < 4;
-      const __amdgpu_buffer_rsrc_t r = c2 ? W2r : W3r;
-      const int vo = c2 ? v2k : v3k;
-      const int so = c2 ? (j * 16 * 512 + u * 2048) : (j * 16 * 576 + (u - 4) * 2048);
-      const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
-      const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so + 16, 0);
+      const int blk = (u < 4 ? 0 : kWk3) + (((2 * half + j) * 4 + (u & 3)) * 2) * 1024 + lane * 16;
+      const u32x4 lo = *reinterpret_cast<const u32x4*>(&wk[blk]);
+      const u32x4 hi = *reinterpret_cast<const u32x4*>(&wk[blk + 1024]);
       w[j] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
     }
   };
@@ -326,6 +333,32 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   for (int k = tid; k < 12 * 64; k += kThreads) {
     const int hs = k >> 6, l = k & 63, h2 = hs / 6, s2 = hs % 6;
     *reinterpret_cast<V*>(&w1l[k * 8 * EB]) = Fr::ld(W1 + (w1row(h2, l & 15) * 256 + 32 * s2 + 8 * (l >> 4)) * EB);
+  }
+  if constexpr (K8) {
+    // the K = 128 weight copies (fragment-major in memory: per fragment, 16
+    // rows x K bytes, K = 128 units of 32 bytes per lane, then K = 32 units
+    // of 8) into the LDS layout, 16 bytes per thread and pass
+    const unsigned char* W2k = reinterpret_cast<const unsigned char*>(a.w[1]);
+    const unsigned char* W3k = reinterpret_cast<const unsigned char*>(a.w[2]);
+    for (int c = tid; c < kWkBytes / 16; c += kThreads) {
+      const unsigned char* src;
+      int dst;
+      if (c < 4096) {                     // K = 128 units: c = ((cf * 4 + s) * 64 + lane) * 2 + part
+        const int c3 = c >= 2048, cc = c & 2047;
+        const int part = cc & 1, ln = (cc >> 1) & 63, us = cc >> 7;
+        src = c3 ? W3k + (us >> 2) * 16 * 576 + ((us & 3) * 64 + ln) * 32 + part * 16 : W2k + cc * 16;
+        // conv3: lane group g of a step takes tap offset g & 1 and channel
+        // half g >> 1 (the bank-friendly order of its pixel reads), which in
+        // memory is lane group 2 (g & 1) + (g >> 1): the two index bits swap
+        const int lg = c3 ? ((((ln >> 4) & 1) << 1) | (ln >> 5)) : (ln >> 4);
+        dst = (c3 ? kWk3 : 0) + (us * 2 + part) * 1024 + ((ln & 15) + 16 * lg) * 16;
+      } else {                            // conv3's K = 32 units: 1 KB per fragment
+        const int cc = c - 4096;
+        src = W3k + (cc >> 6) * 16 * 576 + 4 * 2048 + (cc & 63) * 16;
+        dst = kWkTail + cc * 16;
+      }
+      *reinterpret_cast<u32x4*>(&wk[dst]) = *reinterpret_cast<const u32x4*>(src);
+    }
   }
   V w1c[2][2];
 #pragma unroll
@@ -404,7 +437,6 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
   for (int r0 = 0; r0 < G; r0 += T) {
     const int nt = (G - r0) < T ? (G - r0) : T;
     V wr[kRing][2];      // conv2 / conv3 weight ring (its first kD steps load during conv1)
-    v8i wr8[kRing8][2];  // the same for K8 (kD8 steps ahead)
     lds_barrier();       // the round's frames are staged
 
     // ---- conv1: S + channel 3 of each item -> x1 ----
@@ -458,10 +490,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       // vector-memory path (8 wavefronts x 2 KB per step), which conv1 does
       // not otherwise use, so spread out they overlap conv1's work.
       auto ring_part = [&](int j) {
-        if constexpr (K8) {
-#pragma unroll
-          for (int u = j * kD8 / T; u < (j + 1) * kD8 / T; ++u) wstep8(u, wr8[u % kRing8]);
-        } else {
+        if constexpr (!K8) {
 #pragma unroll
           for (int u = j * kD / T; u < (j + 1) * kD / T; ++u) wstep(u, wr[u % kRing]);
         }
@@ -503,8 +532,8 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
     if constexpr (K8) {
     // ---- conv2 and conv3 on the K = 128 instruction ----
     // conv2 step s (s = 0..3): lane group g holds tap (kh = s, kw = g), all
-    // 32 channels; conv3 step s (s = 0..3): tap 2s + g/2, channels
-    // 32 (g & 1) .. +31; then conv3's ninth tap as two K = 32 steps.
+    // 32 channels; conv3 step s (s = 0..3): tap 2s + (g & 1), channels
+    // 32 (g >> 1) .. +31; then conv3's ninth tap as two K = 32 steps.
     {
       const int rows2 = nt * 81;
       f32x4 acc[F2W][2];
@@ -514,9 +543,12 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       for (int i = 0; i < F2W; ++i) {
         const int r = (fq + 4 * i) * 16 + r16;
         ok[i] = r < rows2;
-        const int rr = ok[i] ? r : 0;
+        // rows past the round's items read some in-bounds pixel (results
+        // unused): their own slot, or 16 rows back past the last item, which
+        // keeps the cycle's bank groups distinct
+        const int rr = r < T * 81 ? r : r - 16;
         const int t = rr / 81, p = rr % 81;
-        base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P;
+        base[i] = t * L::X1T + ((p / 9) * L::X1W + (p % 9)) * L::X1P;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
       // (gp: the lane group, re-derived here so that the compiler keeps the
@@ -525,33 +557,36 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       int gp = g;
       asm volatile("" : "+v"(gp));
       auto koff2 = [&](int st) {   // this lane's tap (kh = st, kw = g)
-        return ((st & 1) * 2 + (gp & 1)) * L::X1PH + ((st >> 1) * 10 + (gp >> 1)) * L::X1P;
+        return ((st & 1) * 2 + (gp & 1)) * L::X1PH + ((st >> 1) * L::X1W + (gp >> 1)) * L::X1P;
       };
       auto ld32 = [](const unsigned char* q) {
         const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
         const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
         return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       };
-      // Weight step u sits in ring slot u % 3 (the step's, the next one's and
-      // the one requested kD8 = 2 steps ahead), so the steps rotate by slot
-      // index, not by register copies: a copy of a register still being
-      // loaded makes the wavefront wait for that load, which cut the
-      // lookahead to one step.  A scheduling barrier closes every step, so
-      // the compiler cannot hoist a later step's pixel reads and run out of
-      // registers.
+      // A step reads the next step's weights, and each fragment the next
+      // fragment's pixels (the last one the next step's first), one ahead;
+      // the steps rotate by slot index (compile-time after unrolling).  A
+      // scheduling barrier closes every step, so the compiler cannot hoist a
+      // later step's reads and run out of registers.
+      v8i wq[2][2], pv[2];
+      wlds(0, wq[0]);
+      pv[0] = ld32(&x1[base[0] + koff2(0)]);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        wstep8(st + 2, wr8[(st + 2) % kRing8]);   // steps 2..5: conv2's last two, conv3's first two
+        if (st + 1 < 4) wlds(st + 1, wq[(st + 1) & 1]);
         const int ko = koff2(st);
-        v8i pv[2];
-        pv[0] = ld32(&x1[base[0] + ko]);
 #pragma unroll
         for (int i = 0; i < F2W; ++i) {
-          if (i + 1 < F2W) pv[(i + 1) & 1] = ld32(&x1[base[i + 1] + ko]);   // clamped rows
+          const int n = st * F2W + i;      // pixel operand slot n & 1
+          if (i + 1 < F2W) pv[(n + 1) & 1] = ld32(&x1[base[i + 1] + ko]);   // clamped rows
+          else if (st + 1 < 4) pv[(n + 1) & 1] = ld32(&x1[base[0] + koff2(st + 1)]);
+          __builtin_amdgcn_sched_barrier(0);   // the next fragment's read goes out before these
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wr8[st % kRing8][j], pv[i & 1], acc[i][j],
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wq[st & 1][j], pv[n & 1], acc[i][j],
                                                                           0, 0, 0, 127, 0, 127);
+          __builtin_amdgcn_sched_barrier(0);
         }
         pin_acc(acc);
         __builtin_amdgcn_sched_barrier(0);
@@ -585,7 +620,7 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       for (int i = 0; i < F3W; ++i) {
         const int r = (fq + 4 * i) * 16 + r16;
         ok[i] = r < rows3;
-        const int rr = ok[i] ? r : 0;
+        const int rr = r < T * 49 ? r : r - 16;   // as in conv2
         const int p = rr % 49;
         pt[i] = rr / 49;
         base[i] = pt[i] * L::X2T + ((p / 7) * 9 + (p % 7)) * L::X2P;
@@ -593,44 +628,43 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
       }
       int gp = g;                  // (re-derived in the round, as in conv2)
       asm volatile("" : "+v"(gp));
-      auto koff3 = [&](int st) {   // this lane's tap 2 st + g/2, channels 32 (g & 1)
-        const int kk = 2 * st + (gp >> 1);
-        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (gp & 1);
+      auto koff3 = [&](int st) {   // this lane's tap 2 st + (g & 1), channels 32 (g >> 1)
+        const int kk = 2 * st + (gp & 1);
+        return ((kk / 3) * 9 + kk % 3) * L::X2P + 32 * (gp >> 1);
       };
       auto ld32 = [](const unsigned char* q) {
         const u32x4 lo = *reinterpret_cast<const u32x4*>(q);
         const u32x4 hi = *reinterpret_cast<const u32x4*>(q + 16);
         return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       };
-      // the ninth tap's weights (two K = 32 units of 8 bytes per lane),
-      // requested with the last ring step's loads
-      V wt[2][2];
+      v8i wq[2][2], pv[2];
+      wlds(4, wq[0]);
+      pv[0] = ld32(&ux[base[0] + koff3(0)]);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        if (st < 2) wstep8(st + 6, wr8[(st + 6) % kRing8]);   // steps 6, 7 (conv3's last two)
-        if (st == 2) {
-#pragma unroll
-          for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-              wt[t][j] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(
-                                                   W3r, half * 2 * 16 * 576 + lane * 8,
-                                                   j * 16 * 576 + 4 * 2048 + t * 512, 0));
-        }
+        if (st + 1 < 4) wlds(st + 5, wq[(st + 1) & 1]);
         const int ko = koff3(st);
-        v8i pv[2];
-        pv[0] = ld32(&ux[base[0] + ko]);
 #pragma unroll
         for (int i = 0; i < F3W; ++i) {
-          if (i + 1 < F3W) pv[(i + 1) & 1] = ld32(&ux[base[i + 1] + ko]);   // clamped rows
+          const int n = st * F3W + i;
+          if (i + 1 < F3W) pv[(n + 1) & 1] = ld32(&ux[base[i + 1] + ko]);   // clamped rows
+          else if (st + 1 < 4) pv[(n + 1) & 1] = ld32(&ux[base[0] + koff3(st + 1)]);
+          __builtin_amdgcn_sched_barrier(0);   // the next fragment's read goes out before these
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wr8[(st + 4) % kRing8][j], pv[i & 1],
-                                                                          acc[i][j], 0, 0, 0, 127, 0, 127);
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wq[st & 1][j], pv[n & 1], acc[i][j],
+                                                                          0, 0, 0, 127, 0, 127);
+          __builtin_amdgcn_sched_barrier(0);
         }
         pin_acc(acc);
         __builtin_amdgcn_sched_barrier(0);
       }
+      // the ninth tap's weights: two K = 32 units of 8 bytes per lane
+      V wt[2][2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) wt[t][j] = Fr::ld(&wk[kWkTail + (2 * half + j) * 1024 + (t * 64 + lane) * 8]);
       // tap 8 (kh = 2, kw = 2): K = 32 steps t = 0, 1 over channels 32t + 8g .. +7
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -681,14 +715,14 @@ __global__ void __launch_bounds__(kThreads, 1) conv_fused_kernel(FusedConvArgs a
         ok[i] = r < rows2;
         const int rr = ok[i] ? r : 0;
         const int t = rr / 81, p = rr % 81;
-        base[i] = t * L::X1T + ((p / 9) * 10 + (p % 9)) * L::X1P + 8 * g * EB;
+        base[i] = t * L::X1T + ((p / 9) * L::X1W + (p % 9)) * L::X1P + 8 * g * EB;
         acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
       // conv2 K step s: kernel row kh = s/4, column kw = s%4; lane group g
       // holds input channels 8g..8g+7 of that tap
       auto koff2 = [](int s) {
         const int kh = s >> 2, kw = s & 3;
-        return ((kh & 1) * 2 + (kw & 1)) * L::X1PH + ((kh >> 1) * 10 + (kw >> 1)) * L::X1P;
+        return ((kh & 1) * 2 + (kw & 1)) * L::X1PH + ((kh >> 1) * L::X1W + (kw >> 1)) * L::X1P;
       };
       V pv[2][F2W];
 #pragma unroll
@@ -872,16 +906,15 @@ void launch_conv_fused(int prec, int T, const FusedConvArgs& args, int n_groups,
   if (n_groups <= 0) return;
   typedef void (*Kern)(FusedConvArgs);
   // BF16 at T = 4 exceeds the LDS of one CU: T <= 3; FP8 takes T <= 4 with
-  // the K = 32 instruction and 3..5 with the K = 128 one; other values take 3
+  // the K = 32 instruction and 3 with the K = 128 one (its weights take 68 KB
+  // of LDS); other values take 3
   k8 = k8 && prec == P_FP8;
-  const int Tk = k8 ? ((T == 4 || T == 5) ? T : 3)
-                    : (T == 1 || T == 2 || (T == 4 && prec != P_BF16)) ? T : 3;
+  const int Tk = k8 ? 3 : (T == 1 || T == 2 || (T == 4 && prec != P_BF16)) ? T : 3;
   Kern k;
   if (prec == P_BF16) {
     k = Tk == 1 ? conv_fused_kernel<P_BF16, 1> : Tk == 2 ? conv_fused_kernel<P_BF16, 2> : conv_fused_kernel<P_BF16, 3>;
   } else if (k8) {
-    k = Tk == 4 ? conv_fused_kernel<P_FP8, 4, true> : Tk == 5 ? conv_fused_kernel<P_FP8, 5, true>
-                                                              : conv_fused_kernel<P_FP8, 3, true>;
+    k = conv_fused_kernel<P_FP8, 3, true>;
   } else {
     k = Tk == 1 ? conv_fused_kernel<P_FP8, 1> : Tk == 2 ? conv_fused_kernel<P_FP8, 2>
         : Tk == 4 ? conv_fused_kernel<P_FP8, 4> : conv_fused_kernel<P_FP8, 3>;
