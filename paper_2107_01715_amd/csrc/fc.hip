@@ -23,12 +23,13 @@
 //
 // A direct load writes lane l's 16 bytes at slot l of the instruction's 1 KB
 // window, so the bank-conflict swizzle is applied on the global side: LDS
-// slot (row r, chunk pc) holds the tile's K chunk pc ^ ((r >> 2) & 2).  A
+// slot (row r, chunk pc) holds the tile's K chunk pc ^ ((r >> 2) & m).  A
 // 16-byte LDS read serves each 32-lane half of a wavefront in two cycles, one
 // per parity of lane bits 2, 3 and 4, and a cycle is conflict-free when its
 // 16 lanes touch 16 distinct 16-byte bank groups (64 banks of 4 bytes); for
-// an operand read (lane = 16 x chunk group + row) this swizzle gives every
-// cycle 16 distinct groups, where a plain or (r >> 2) & 3 layout gives 8.
+// a BF16 operand read (lane = 16 x chunk group + row) m = 2 gives every
+// cycle 16 distinct groups, where a plain or m = 3 layout gives 8.  FP8
+// operand reads are 8 bytes and take m = 3 (see swz).
 // Each stage ends its wavefront's own loads (s_waitcnt vmcnt) before one
 // workgroup barrier; the slot a load refills was last read two stages
 // earlier, before a barrier every wavefront has passed.
@@ -111,8 +112,16 @@ template <> struct FT<P_FP8> {
   }
 };
 
-// byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B half
-__device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ ((r >> 2) & 2)) << 4); }
+// byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B
+// half.  BF16 operand reads are 16 bytes (lane = 16 x chunk group + row):
+// chunk c ^ ((r >> 2) & 2).  FP8 operand reads are 8 bytes, served 32 lanes
+// per cycle, each cycle conflict-free when its 32 lanes touch 32 distinct
+// 8-byte bank pairs: chunk c ^ ((r >> 2) & 3) gives the 16 rows x 2 halves
+// of a chunk group 32 distinct pairs (the BF16 swizzle gives 16).
+template <int EB> __device__ __forceinline__ int swz_mask() { return EB == 1 ? 3 : 2; }
+template <int EB> __device__ __forceinline__ int swz(int r, int c) {
+  return r * kRB + ((c ^ ((r >> 2) & swz_mask<EB>())) << 4);
+}
 
 template <int P>
 __global__ void __launch_bounds__(kThreads, 1)
@@ -151,7 +160,7 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = wave * 2 + j, ps = q * 64 + lane;
-    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & 2);
+    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & swz_mask<EB>());
     srcA[j] = X + fc1_tiled_offset(m0 + r, c * 16, EB);
     srcB[j] = W + fc1_tiled_offset(n0 + r, c * 16, EB);
     dst[j] = q * 1024;                              // wave-uniform LDS window
@@ -189,10 +198,10 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
       const int c = kb >> 4, cb = kb & 15;
       V xv[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz(wm * 64 + j * 16 + r16, c) + cb);
+      for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz<EB>(wm * 64 + j * 16 + r16, c) + cb);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const V wv = *reinterpret_cast<const V*>(Bs + swz(wn * 128 + i * 16 + r16, c) + cb);
+        const V wv = *reinterpret_cast<const V*>(Bs + swz<EB>(wn * 128 + i * 16 + r16, c) + cb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
       }
