@@ -114,14 +114,12 @@ template <> struct FT<P_FP8> {
 
 // byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B
 // half.  BF16 operand reads are 16 bytes (lane = 16 x chunk group + row):
-// chunk c ^ ((r >> 2) & 2).  FP8 operand reads are 8 bytes, served 32 lanes
-// per cycle, each cycle conflict-free when its 32 lanes touch 32 distinct
-// 8-byte bank pairs: chunk c ^ ((r >> 2) & 3) gives the 16 rows x 2 halves
-// of a chunk group 32 distinct pairs (the BF16 swizzle gives 16).
-template <int EB> __device__ __forceinline__ int swz_mask() { return EB == 1 ? 3 : 2; }
-template <int EB> __device__ __forceinline__ int swz(int r, int c) {
-  return r * kRB + ((c ^ ((r >> 2) & swz_mask<EB>())) << 4);
-}
+// chunk c ^ ((r >> 2) & 2).  FP8 operands are read for the K = 128
+// instruction: lane group g takes chunks 2 (g & 1) and 2 (g & 1) + 1 of
+// stage 2p + (g >> 1), and chunk c ^ ((r >> 3) & 1) gives every cycle of
+// those 16-byte reads 16 distinct bank groups (either BF16 form gives 8).
+template <int EB> __device__ __forceinline__ int swz_x(int r) { return EB == 1 ? ((r >> 3) & 1) : ((r >> 2) & 2); }
+template <int EB> __device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ swz_x<EB>(r)) << 4); }
 
 template <int P>
 __global__ void __launch_bounds__(kThreads, 1)
@@ -160,7 +158,7 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = wave * 2 + j, ps = q * 64 + lane;
-    const int r = ps >> 2, c = (ps & 3) ^ ((r >> 2) & swz_mask<EB>());
+    const int r = ps >> 2, c = (ps & 3) ^ swz_x<EB>(r);
     srcA[j] = X + fc1_tiled_offset(m0 + r, c * 16, EB);
     srcB[j] = W + fc1_tiled_offset(n0 + r, c * 16, EB);
     dst[j] = q * 1024;                              // wave-uniform LDS window
@@ -182,28 +180,93 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  if constexpr (P == P_FP8) {
+    // K = 128 instruction over stage pairs (2p, 2p + 1), one barrier per
+    // pair; an odd last stage runs on the K = 32 instruction after them.
+    // Pair p refills the two slots pair p - 1 read (stages 2p + 3, 2p + 4),
+    // after its barrier, which every wavefront passes only once it has
+    // finished pair p - 1; stage 2p + 2 is then in flight from pair p - 1.
+    typedef __attribute__((ext_vector_type(8))) int v8i;
+    typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+    auto ld32 = [](const unsigned char* base, int row, int c) {
+      const u32x4 lo = *reinterpret_cast<const u32x4*>(base + swz<EB>(row, c));
+      const u32x4 hi = *reinterpret_cast<const u32x4*>(base + swz<EB>(row, c + 1));
+      return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+    };
+    static_assert(kAhead == 3 && kNS == 5, "the pair schedule assumes 5 slots, 3 stages issued ahead");
 #pragma unroll
-  for (int st = 0; st < kAhead; ++st) issue(st);
-  for (int st = 0; st < NST; ++st) {
-    if (st + kAhead < NST) issue(st + kAhead);
-    const int later = (NST - 1 - st) < kAhead ? (NST - 1 - st) : kAhead;   // stages issued after st
-    wait_vm(4 * later);
-    lds_barrier();
-    const unsigned char* As = ring[st % kNS];
-    const unsigned char* Bs = As + kBM * kRB;
+    for (int st = 0; st < kAhead; ++st) issue(st);
+    for (int pp = 0; pp < NST / 2; ++pp) {
+      wait_vm(2 * pp + 2 < NST ? 4 : 0);            // stage 2p + 2 may stay in flight
+      lds_barrier();
+      if (2 * pp + 3 < NST) issue(2 * pp + 3);
+      if (2 * pp + 4 < NST) issue(2 * pp + 4);
+      // this lane's K chunk: stage 2p + (g >> 1), bytes 32 (g & 1) .. +31
+      const unsigned char* As = ring[(2 * pp + (g >> 1)) % kNS];
+      const unsigned char* Bs = As + kBM * kRB;
+      const int c0 = 2 * (g & 1);
+      // neuron fragment i + 1's operand is read before fragment i's MFMAs
+      // (two register sets; scheduling barriers keep that order, else the
+      // compiler hoists all eight reads and runs out of registers)
+      v8i xv[4], wv[2];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      // this lane's 8 K values of step ks: byte 32 * ks * EB / ... within the row
-      const int kb = ks * 32 * EB + 8 * g * EB;        // byte offset in the row's 64 bytes
-      const int c = kb >> 4, cb = kb & 15;
-      V xv[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz<EB>(wm * 64 + j * 16 + r16, c) + cb);
+      for (int j = 0; j < 4; ++j) xv[j] = ld32(As, wm * 64 + j * 16 + r16, c0);
+      wv[0] = ld32(Bs, wn * 128 + r16, c0);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const V wv = *reinterpret_cast<const V*>(Bs + swz<EB>(wn * 128 + i * 16 + r16, c) + cb);
+        if (i + 1 < 8) wv[(i + 1) & 1] = ld32(Bs, wn * 128 + (i + 1) * 16 + r16, c0);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wv[i & 1], xv[j], acc[i][j], 0, 0, 0, 127, 0,
+                                                                        127);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if constexpr (NST & 1) {
+      wait_vm(0);
+      lds_barrier();
+      const unsigned char* As = ring[(NST - 1) % kNS];
+      const unsigned char* Bs = As + kBM * kRB;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kb = ks * 32 * EB + 8 * g * EB;
+        const int c = kb >> 4, cb = kb & 15;
+        V xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz<EB>(wm * 64 + j * 16 + r16, c) + cb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const V wv = *reinterpret_cast<const V*>(Bs + swz<EB>(wn * 128 + i * 16 + r16, c) + cb);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int st = 0; st < kAhead; ++st) issue(st);
+    for (int st = 0; st < NST; ++st) {
+      if (st + kAhead < NST) issue(st + kAhead);
+      const int later = (NST - 1 - st) < kAhead ? (NST - 1 - st) : kAhead;   // stages issued after st
+      wait_vm(4 * later);
+      lds_barrier();
+      const unsigned char* As = ring[st % kNS];
+      const unsigned char* Bs = As + kBM * kRB;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        // this lane's 8 K values of step ks: byte 32 * ks * EB / ... within the row
+        const int kb = ks * 32 * EB + 8 * g * EB;        // byte offset in the row's 64 bytes
+        const int c = kb >> 4, cb = kb & 15;
+        V xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const V*>(As + swz<EB>(wm * 64 + j * 16 + r16, c) + cb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const V wv = *reinterpret_cast<const V*>(Bs + swz<EB>(wn * 128 + i * 16 + r16, c) + cb);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = Ft::mma(wv, xv[j], acc[i][j]);
+        }
       }
     }
   }
