@@ -136,6 +136,26 @@ def _profile_value(path, pattern):
     return float(m.group(1))
 
 
+EXPAND_PROFILE = os.path.join(ROOT, "profiles", "expand_256roots_A18_d3_traffic.md")
+
+
+def measured_expand_traffic():
+    """HBM bytes per new node of the expansion (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated) while its kernel's source is the one measured."""
+    import hashlib
+    import re
+    try:
+        text = open(EXPAND_PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_2107_01715_amd", "csrc", "expand.hip"), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_node:\s*([0-9.]+)", text)
+    h = re.search(r"source_sha256 expand.hip:\s*([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != hashlib.sha256(src).hexdigest():
+        return None
+    return float(m.group(1))
+
+
 def measured_traffic(kernel, precision, fused, tuned):
     """HBM bytes per stack of the dominant kernel (FETCH_SIZE + WRITE_SIZE,
     copy-calibrated), for the kernel and round size it was measured on.  The
@@ -510,7 +530,7 @@ def run_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8", "fp32"])
     ap.add_argument("--cpu-sample", type=int, default=64, help="roots timed through the oracle (0 = skip)")
@@ -800,7 +820,10 @@ def main():
         "qnet_stage_tflops": qnet_tflops,
         "expand": {"bound": "hbm", "achieved": exp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": exp_gbs / HBM_PEAK_GBS if exp_gbs else None, "nodes": exp_nodes,
-                   "bytes_per_node": EXPAND_BYTES_PER_NODE},
+                   "bytes_per_node": EXPAND_BYTES_PER_NODE,
+                   "traffic_bytes_per_node": measured_expand_traffic(),
+                   "achieved_is": "algorithmic bytes per node x new nodes / HIP-event time of the three launches; "
+                                  "traffic_bytes_per_node from rocprofv3 FETCH_SIZE + WRITE_SIZE"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
