@@ -130,3 +130,37 @@ def test_largest_tree_a18_depth4(lib, headline):
     rel = np.abs(q1.astype(np.float64) - q32).max(axis=1) / np.abs(q32).max(axis=1)
     print(f"A=18 d=4 BF16 vs FP32: rel err {np.round(rel, 5)}")
     assert rel.max() < 2e-2, rel
+
+
+def test_fp8_instruction_paths_agree_at_full_size(lib, headline):
+    """FP8 at the headline shape in the benchmark's launch shape: the K = 128
+    path (conv2 / conv3 weights in LDS, its own x1 / x2 layouts, fc1 over
+    stage pairs) and the K = 32 path sum each group of 8 products the same way
+    and add the group sums in the same order, so the two must give the same
+    bits on all 256 roots; so must another chunking of the stacks.  (The FP8
+    emulation needs about 20 minutes per root at this size; it is checked
+    against the kernels on sibling groups of 18 and on A = 18, depth-2 roots.)"""
+    ctx = headline[0]
+    pos, st = W.roots(INSTANCE_SEED, N)
+    corr = lib.correction(True, 1.0)
+    _, cal = W.roots(2003, 64)
+    ctx.calibrate_fp8(cal)
+    ctx.set_precision(lib.FP8)
+    out = {}
+    try:
+        for k128, chunk in ((1, 1048576), (0, 1048576), (1, 262144)):
+            ctx.set_tuning(lib.TUNE_FP8_K128, k128)
+            ctx.set_tuning(lib.TUNE_FUSED_CHUNK, chunk)
+            out[(k128, chunk)] = ctx.search(pos, st, D, A, GAMMA, corr)
+    finally:
+        ctx.set_tuning(lib.TUNE_FP8_K128, 1)
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 1048576)
+        ctx.set_precision(lib.FP32)
+    a, q = out[(1, 1048576)]
+    for key in ((0, 1048576), (1, 262144)):
+        assert np.array_equal(out[key][0], a), key
+        assert np.array_equal(out[key][1], q), key
+    _, (a32, q32), _, _, _ = headline
+    agree = sum(int(a[r] == a32[r] or q32[r][a[r]] >= q32[r].max() - 1e-6 * max(1.0, abs(q32[r].max())))
+                for r in range(N))
+    print(f"FP8 vs FP32 root actions: {agree}/{N}")
