@@ -139,3 +139,4 @@ def test_graph_handle_is_reusable(lib):
         if g is not None:
             g.close()
         ctx.close()
+
