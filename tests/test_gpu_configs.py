@@ -139,4 +139,3 @@ def test_graph_handle_is_reusable(lib):
         if g is not None:
             g.close()
         ctx.close()
-
