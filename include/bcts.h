@@ -222,7 +222,9 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          (BF16 caps at 3: a round of 4 exceeds the LDS)
  *   BCTS_TUNE_FUSED_CHUNK  stacks per Q-network chunk on the fused path
  *   BCTS_TUNE_LAYER_CHUNK  stacks per chunk on the layer-by-layer path
- *                          (also the FP32 correction evaluations below)
+ *                          (also the FP32 correction evaluations below);
+ *                          default 65,536 (about 100 KB of FP32 workspace
+ *                          per stack)
  *   BCTS_TUNE_CORR_FP32    1 = (default) the Q-network inputs of the
  *                          correction -- Q(s_0, .), which fixes pi_o, and the
  *                          depth-1 values of the Bellman errors (Prop. 3.6)
@@ -249,7 +251,13 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          (rounds of 1..4).
  *                          The products of each 8 consecutive K values are
  *                          summed the same way by both, so the results are
- *                          the same up to FP32 addition order.             */
+ *                          the same up to FP32 addition order.
+ *   BCTS_TUNE_CONV1_GROUPS layer-by-layer path (FP32, the FP32 correction
+ *                          evaluations, BCTS_TUNE_FUSED = 0): 1 (default) =
+ *                          conv1 sums the channels a sibling group's stacks
+ *                          share (0..2) once per group and adds each
+ *                          sibling's channel 3 to that partial sum, 0 = every
+ *                          stack alone.  Same results, bit for bit.        */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
@@ -257,7 +265,8 @@ typedef enum {
   BCTS_TUNE_LAYER_CHUNK = 3,
   BCTS_TUNE_CORR_FP32 = 4,
   BCTS_TUNE_MLP_CROSSOVER = 5,
-  BCTS_TUNE_FP8_K128 = 6
+  BCTS_TUNE_FP8_K128 = 6,
+  BCTS_TUNE_CONV1_GROUPS = 7
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);
@@ -410,8 +419,9 @@ bcts_status bcts_debug_qnet(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int
  * stacks (the last group may be shorter), the grouping a search gives the A
  * children of one node (Alg. 1: a child's stack is its parent's last three
  * frames plus its own): the stacks of a group must share channels 0..2
- * (BCTS_E_INVAL otherwise).  The fused BF16/FP8 kernel then computes the
- * shared channels' part of conv1 once per group, as in a search.           */
+ * (BCTS_E_INVAL otherwise).  The fused BF16/FP8 kernel, and the layer
+ * path's conv1 under BCTS_TUNE_CONV1_GROUPS, then compute the shared
+ * channels' part of conv1 once per group, as in a search.                  */
 bcts_status bcts_debug_qnet_siblings(bcts_ctx* ctx, int32_t n, const uint8_t* stacks, int32_t A,
                                      int32_t group, float* out_q);
 /* Kernel timing with HIP events on the search's own stream.  While enabled,

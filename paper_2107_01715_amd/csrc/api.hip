@@ -26,6 +26,7 @@
 
 #include "../../include/bcts.h"
 #include "bcts_internal.h"
+#include "qnet_groups.h"
 #include "plan.h"
 #include "mlp_host.h"
 
@@ -51,10 +52,11 @@ struct bcts_ctx {
   bool env_set = false, qnet_set = false;
   EnvTables env{};
   int prec = P_FP32;
-  long long chunk_items = 8192;        // layer-by-layer path (FP32)
+  long long chunk_items = 65536;       // layer-by-layer path (FP32): ~6.6 GB of FP32 workspace
   long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
   bool fp8_k128 = true;                 // FP8 conv2 / conv3 on the K = 128 matrix instruction
+  bool conv1_groups = true;             // layer path: conv1's shared channels once per sibling group
   bool fused = true;
   bool corr_fp32 = true;                // root / depth-1 evals of corrected roots in FP32
   int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
@@ -357,7 +359,8 @@ bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* de
   const long long cnt = ch.i1 - ch.i0;
   launch_item_desc(ch.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
   if (!p.fused) {
-    launch_qnet(c->prec, c->q, desc, cnt, ws, V + ch.i0, q0, s, cev);
+    const ChunkGroups cg{groups + ch.g0, c->conv1_groups ? ch.g1 - ch.g0 : 0, ch.i0};
+    launch_qnet_groups(c->prec, c->q, desc, cnt, cg, ws, V + ch.i0, q0, s, cev);
     return BCTS_OK;
   }
   const QnetDev& q = c->q;
@@ -400,11 +403,12 @@ bcts_status enqueue_tail(bcts_ctx* c, const Plan& p, char* A, ItemDesc* desc, ch
   const RootInfo* roots = reinterpret_cast<const RootInfo*>(A + p.o_roots);
   float* V = reinterpret_cast<float*>(A + p.o_V);
   float* q0 = reinterpret_cast<float*>(A + p.o_q0);
+  const FusedGroup* groups = reinterpret_cast<const FusedGroup*>(A + p.o_groups);
   for (const auto& tc : p.tail_chunks) {
-    const long long cnt = tc.second - tc.first;
-    launch_item_desc(tc.first, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc,
-                     s);
-    launch_qnet(P_FP32, c->q, desc, cnt, ws, V + tc.first, q0, s, nullptr);
+    const long long cnt = tc.i1 - tc.i0;
+    launch_item_desc(tc.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
+    const ChunkGroups cg{groups + tc.g0, c->conv1_groups ? tc.g1 - tc.g0 : 0, tc.i0};
+    launch_qnet_groups(P_FP32, c->q, desc, cnt, cg, ws, V + tc.i0, q0, s, nullptr);
   }
   return BCTS_OK;
 }
@@ -1587,11 +1591,11 @@ bcts_status debug_qnet_impl(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32
   bcts_correction off{0, 0.f, 0};
   Plan p;
   plan_search(c, p, n, dep.data(), Av.data(), 1.f, off, kMaxA, true);
-  if (group > 1 && p.fused) {
+  if (group > 1) {
     // regroup the one-item root groups into sibling groups, chunks of whole groups
     p.groups.clear();
     for (long long i = 0; i < n; i += group) p.groups.push_back(FusedGroup{i, (int)std::min<long long>(group, n - i), 0});
-    const long long target = std::max(1LL, c->fused_chunk_items);
+    const long long target = std::max(1LL, p.fused ? c->fused_chunk_items : c->chunk_items);
     p.chunks.clear();
     int g = 0;
     while (g < (int)p.groups.size()) {
@@ -1775,6 +1779,9 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
     case BCTS_TUNE_CORR_FP32:
       c->corr_fp32 = value != 0;
       return BCTS_OK;
+    case BCTS_TUNE_CONV1_GROUPS:
+      c->conv1_groups = value != 0;
+      return BCTS_OK;
     default:
       return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
@@ -1790,6 +1797,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_CORR_FP32: *value = c->corr_fp32 ? 1 : 0; return BCTS_OK;
     case BCTS_TUNE_MLP_CROSSOVER: *value = c->mlp_crossover; return BCTS_OK;
     case BCTS_TUNE_FP8_K128: *value = c->fp8_k128 ? 1 : 0; return BCTS_OK;
+    case BCTS_TUNE_CONV1_GROUPS: *value = c->conv1_groups ? 1 : 0; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }

@@ -175,42 +175,39 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     for (int r = 0; r < n; ++r)
       if (p.roots[r].d >= 1) add_corr_segs(r);
   p.n_items = item;
-  {
-    const long long tc = std::max(1LL, tail_chunk_items);
-    for (long long i = p.tail_item0; i < p.n_items; i += tc) {
-      const long long e = std::min(p.n_items, i + tc);
-      p.tail_chunks.emplace_back(i, e);
-      p.tail_chunk = std::max(p.tail_chunk, e - i);
-    }
-  }
   // sibling groups: the A children of each level-(d-1) node, the A depth-1
-  // nodes of a root, a root alone; chunks hold whole groups
-  for (size_t si = 0; si < main_segs; ++si) {
+  // nodes of a root, a root alone; the main items' groups, then the tail's
+  int main_groups = 0;
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    if (si == main_segs) main_groups = (int)p.groups.size();
     const Seg& sg = p.segs[si];
     const RootInfo& ri = p.roots[sg.root];
     const long long cnt = sg.kind == 2 ? 1 : (sg.kind == 1 ? ri.A : ri.lcnt[ri.d]);
     const int gsz = sg.kind == 2 ? 1 : ri.A;
     for (long long j = 0; j < cnt; j += gsz) p.groups.push_back(FusedGroup{sg.item0 + j, gsz, 0});
   }
-  {
-    const long long target = std::max(1LL, chunk_items);
-    int g = 0;
-    p.chunk = 1;
-    while (g < (int)p.groups.size()) {
+  if (main_segs == p.segs.size()) main_groups = (int)p.groups.size();
+  // chunks of whole groups, up to `target` items (or one group if larger)
+  auto chunk_groups = [&](int g, int g_end, long long target, std::vector<Plan::Chunk>& out, long long* most) {
+    target = std::max(1LL, target);
+    while (g < g_end) {
       Plan::Chunk ch;
       ch.g0 = g;
       ch.i0 = p.groups[g].item0;
       long long items = 0;
-      while (g < (int)p.groups.size() && (items == 0 || items + p.groups[g].count <= target)) {
+      while (g < g_end && (items == 0 || items + p.groups[g].count <= target)) {
         items += p.groups[g].count;
         ++g;
       }
       ch.g1 = g;
       ch.i1 = ch.i0 + items;
-      p.chunk = std::max(p.chunk, items);
-      p.chunks.push_back(ch);
+      *most = std::max(*most, items);
+      out.push_back(ch);
     }
-  }
+  };
+  p.chunk = 1;
+  chunk_groups(0, main_groups, chunk_items, p.chunks, &p.chunk);
+  chunk_groups(main_groups, (int)p.groups.size(), tail_chunk_items, p.tail_chunks, &p.tail_chunk);
 
   // arena layout
   size_t o = 0;

@@ -52,16 +52,16 @@ struct Plan {
   long long keep_count[kMaxD + 1] = {0};   // keep-list entries of level k over all roots
   long long chunk = 0;                 // max items of a chunk
   bool fused = false;                  // conv stack fused per sibling group
-  std::vector<FusedGroup> groups;      // sibling groups in item order
+  std::vector<FusedGroup> groups;      // sibling groups in item order (main items, then the tail's)
   struct Chunk { int g0, g1; long long i0, i1; };
-  std::vector<Chunk> chunks;           // whole groups, ~chunk_items items each
+  std::vector<Chunk> chunks;           // whole groups of the main items, ~chunk_items items each
   // The correction's own Q-network inputs (the root and depth-1 evaluations
   // of corrected roots) can run in FP32 whatever the leaf precision: they
   // then occupy the item range [tail_item0, n_items), evaluated by the FP32
-  // layer kernels in the ranges of tail_chunks.  tail_item0 == n_items when
-  // every item runs at the search precision.
+  // layer kernels in tail_chunks (whole groups, ~tail_chunk_items items each).
+  // tail_item0 == n_items when every item runs at the search precision.
   long long tail_item0 = 0;
-  std::vector<std::pair<long long, long long>> tail_chunks;
+  std::vector<Chunk> tail_chunks;
   long long tail_chunk = 0;            // max items of a tail chunk
   size_t o_groups = 0;
   // arena offsets

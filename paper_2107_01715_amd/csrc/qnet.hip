@@ -20,6 +20,7 @@
 // accumulating in FP32.  The 1/255 input scaling is applied to conv1's
 // accumulator; FP8 layers rescale by 1/(input scale * weight scale).
 #include "bcts_internal.h"
+#include "qnet_groups.h"
 
 namespace bcts {
 namespace {
@@ -89,11 +90,9 @@ template <> __device__ __forceinline__ Unit<P_FP8> load_unit<P_FP8>(const uint8_
   Unit<P_FP8> u; u.v = *reinterpret_cast<const uint2*>(p); return u;
 }
 
-// 8 pixels (uint8, 4-byte aligned) -> operand unit; fp8 scales the pixel
-template <int P> __device__ __forceinline__ Unit<P> pix_unit(const uint8_t* p, float s8);
-template <> __device__ __forceinline__ Unit<P_FP32> pix_unit<P_FP32>(const uint8_t* p, float) {
-  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
-  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+// 8 pixels (two little-endian words of uint8) -> operand unit; fp8 scales the pixel
+template <int P> __device__ __forceinline__ Unit<P> pix_cvt(unsigned w0, unsigned w1, float s8);
+template <> __device__ __forceinline__ Unit<P_FP32> pix_cvt<P_FP32>(unsigned w0, unsigned w1, float) {
   Unit<P_FP32> u;
   u.a = make_float4((float)(w0 & 255u), (float)((w0 >> 8) & 255u), (float)((w0 >> 16) & 255u),
                     (float)(w0 >> 24));
@@ -105,9 +104,7 @@ __device__ __forceinline__ unsigned pack_bf2(unsigned a, unsigned b) {
   // integers 0..255 are exact in bf16: the float's top 16 bits
   return (__float_as_uint((float)a) >> 16) | (__float_as_uint((float)b) & 0xFFFF0000u);
 }
-template <> __device__ __forceinline__ Unit<P_BF16> pix_unit<P_BF16>(const uint8_t* p, float) {
-  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
-  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+template <> __device__ __forceinline__ Unit<P_BF16> pix_cvt<P_BF16>(unsigned w0, unsigned w1, float) {
   Unit<P_BF16> u;
   u.v.x = pack_bf2(w0 & 255u, (w0 >> 8) & 255u);
   u.v.y = pack_bf2((w0 >> 16) & 255u, w0 >> 24);
@@ -115,9 +112,7 @@ template <> __device__ __forceinline__ Unit<P_BF16> pix_unit<P_BF16>(const uint8
   u.v.w = pack_bf2((w1 >> 16) & 255u, w1 >> 24);
   return u;
 }
-template <> __device__ __forceinline__ Unit<P_FP8> pix_unit<P_FP8>(const uint8_t* p, float s8) {
-  const unsigned w0 = *reinterpret_cast<const unsigned*>(p);
-  const unsigned w1 = *reinterpret_cast<const unsigned*>(p + 4);
+template <> __device__ __forceinline__ Unit<P_FP8> pix_cvt<P_FP8>(unsigned w0, unsigned w1, float s8) {
   unsigned o[2];
   const unsigned w[2] = {w0, w1};
   for (int h = 0; h < 2; ++h) {
@@ -128,6 +123,10 @@ template <> __device__ __forceinline__ Unit<P_FP8> pix_unit<P_FP8>(const uint8_t
     o[h] = (unsigned)hi;
   }
   Unit<P_FP8> u; u.v = make_uint2(o[0], o[1]); return u;
+}
+// 8 pixels at p (4-byte aligned)
+template <int P> __device__ __forceinline__ Unit<P> pix_unit(const uint8_t* p, float s8) {
+  return pix_cvt<P>(*reinterpret_cast<const unsigned*>(p), *reinterpret_cast<const unsigned*>(p + 4), s8);
 }
 
 // ---- layer geometry -----------------------------------------------------
@@ -284,6 +283,9 @@ struct LayerArgs {
   float* V;                    // fc2: max_a Q per item
   float* q0;                   // fc2: [n_roots][18]
   float* part;                 // FP32 fc1: the K slices' partial sums [kFc1Split][M][512]
+  const FusedGroup* groups;    // conv1 by sibling groups: the chunk's groups
+  int n_groups;
+  long long item_base;         // plan-global index of the chunk's first item
 };
 
 template <int L, int P>
@@ -419,6 +421,173 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
   }
 }
 
+// conv1 over sibling groups.  The stacks of a group (the A children of one
+// node in Alg. 1's leaf level, the A depth-1 nodes of a root) hold the same
+// channels 0..2, so conv1's sum over them, K units 0..23 (stages 0..5), is
+// the same for every sibling.  A workgroup takes 128 rows of (group, output
+// pixel) -- at most two groups, since a group has 400 -- sums the shared
+// stages once, then for each sibling adds channel 3 (stages 6 and 7) to a
+// copy of that partial sum and stores the sibling's rows.  Every output sees
+// the MFMAs of layer_kernel<0, P> in the same order, so the two agree bit
+// for bit; the work per group of A falls from 8A stages to 6 + 2A.
+template <int P>
+__global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) {
+  typedef typename PT<P>::T T;
+  constexpr int S = Lds<P>::S, N = Geo<0>::N, NF = N / 16, K = Geo<0>::K, PIX = Geo<0>::MPI;
+  constexpr int kShared = 6;                    // stages over channels 0..2
+  static_assert(Geo<0>::BN == N && K == 8 * kBKU * 8, "conv1: one column tile, 8 stages");
+  __shared__ __attribute__((aligned(16))) T As[kBM * S];
+  __shared__ __attribute__((aligned(16))) T Bs[N * S];         // the shared stages' weights, streamed
+  __shared__ __attribute__((aligned(16))) T Bo[2][N * S];      // channel 3's two stages, resident
+  __shared__ const uint8_t* own[2][kMaxA];                     // each sibling's channel-3 frame
+  __shared__ const uint8_t* shf[2][3];                         // the two groups' channels 0..2
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = (int)args.M;                    // n_groups * 400 rows (< 2^31: checked by the launcher)
+  const int m0 = (int)blockIdx.x * kBM;
+  const int g_lo = m0 / PIX;
+  const int split = (g_lo + 1) * PIX - m0;      // the tile's rows in group g_lo
+  const bool has_hi = split < kBM && g_lo + 1 < args.n_groups;
+  const FusedGroup glo = args.groups[g_lo];
+  const int i_lo = (int)(glo.item0 - args.item_base), c_lo = glo.count;
+  int i_hi = i_lo, c_hi = 0;
+  if (has_hi) {
+    const FusedGroup ghi = args.groups[g_lo + 1];
+    i_hi = (int)(ghi.item0 - args.item_base);
+    c_hi = ghi.count;
+  }
+  const int smax = c_lo > c_hi ? c_lo : c_hi;
+  const T* W = reinterpret_cast<const T*>(args.w);
+
+  if (tid < 2 * kMaxA) {
+    const int h = tid / kMaxA, sb = tid - h * kMaxA;
+    own[h][sb] = sb < (h ? c_hi : c_lo) ? args.desc[(h ? i_hi : i_lo) + sb].frame[3] : nullptr;
+  } else if (tid < 2 * kMaxA + 6) {
+    const int h = (tid - 2 * kMaxA) / 3, c = (tid - 2 * kMaxA) % 3;
+    shf[h][c] = args.desc[h ? i_hi : i_lo].frame[c];
+  }
+  {
+    // channel 3's weights: units 24..31 of every column, one per thread
+    const int n = tid >> 3, u = tid & 7;
+    st_unit<P>(Bo[u >> 2] + n * S, u & 3, load_unit<P>(W + (long long)n * K + (3 * 8 + u) * 8));
+  }
+  lds_barrier();
+
+  // A: thread owns rows ra, ra + 64 and unit ua of each stage; a row is
+  // (group g_lo + h, output pixel), its window origin at `off` (-1: past M)
+  const int ra = tid >> 2, ua = tid & 3;
+  int off[2], hr[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = ra + 64 * k, m = m0 + r;
+    hr[k] = r >= split;
+    const int pix = m - (g_lo + hr[k]) * PIX;
+    off[k] = m < M ? (pix / 20) * 4 * kFrame + (pix % 20) * 4 : -1;
+  }
+  unsigned raw[2][2];
+  Unit<P> gb;
+  // shared stage t: channel t / 2 of the row's group, rows kh = 4 (t % 2) + ua
+  auto load_shared = [&](int t) {
+    const int U = t * kBKU + ua, c = U >> 3, kh = U & 7;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      raw[k][0] = raw[k][1] = 0u;
+      if (off[k] >= 0) {
+        const uint8_t* q = shf[hr[k]][c] + off[k] + kh * kFrame;
+        raw[k][0] = *reinterpret_cast<const unsigned*>(q);
+        raw[k][1] = *reinterpret_cast<const unsigned*>(q + 4);
+      }
+    }
+    if (tid < N * kBKU) gb = load_unit<P>(W + (long long)(tid >> 2) * K + (t * kBKU + (tid & 3)) * 8);
+  };
+  // channel-3 stage hf (0, 1) of sibling sb
+  auto load_own = [&](int sb, int hf) {
+    const int kh = hf * kBKU + ua;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      raw[k][0] = raw[k][1] = 0u;
+      const uint8_t* f = own[hr[k]][sb];
+      if (off[k] >= 0 && f) {                   // else past M or past the row's group
+        const uint8_t* q = f + off[k] + kh * kFrame;
+        raw[k][0] = *reinterpret_cast<const unsigned*>(q);
+        raw[k][1] = *reinterpret_cast<const unsigned*>(q + 4);
+      }
+    }
+  };
+  auto store_a = [&]() {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) st_unit<P>(As + (ra + 64 * k) * S, ua, pix_cvt<P>(raw[k][0], raw[k][1], args.in_s8));
+  };
+  auto store_b = [&]() {
+    if (tid < N * kBKU) st_unit<P>(Bs + (tid >> 2) * S, tid & 3, gb);
+  };
+
+  f32x4 acc[2][NF], part[2][NF];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // shared stages
+  load_shared(0);
+  store_a();
+  store_b();
+  lds_barrier();
+  for (int t = 0; t < kShared; ++t) {
+    if (t + 1 < kShared) load_shared(t + 1);
+    else load_own(0, 0);
+    mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
+    lds_barrier();
+    store_a();
+    if (t + 1 < kShared) store_b();
+    lds_barrier();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) part[i][j] = acc[i][j];
+
+  // siblings: channel 3 on a copy of the partial sum, then the sibling's rows.
+  // Row index of the output: item * 400 + pix = m + (i_h - g_h) * 400.
+  const int col = lane & 15, rq = (lane >> 4) * 4;
+  const int d_lo = (i_lo - g_lo) * PIX, d_hi = (i_hi - g_lo - 1) * PIX;
+  T* out = reinterpret_cast<T*>(args.out);
+  for (int sb = 0; sb < smax; ++sb) {
+    load_own(sb, 1);
+    mma_stage<P, NF>(As + wave * 32 * S, Bo[0], lane, acc);
+    lds_barrier();
+    store_a();
+    lds_barrier();
+    const bool more = sb + 1 < smax;
+    if (more) load_own(sb + 1, 0);
+    mma_stage<P, NF>(As + wave * 32 * S, Bo[1], lane, acc);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = wave * 32 + i * 16 + rq + q, m = m0 + rr;
+        const int h = rr >= split;
+        if (m < M && sb < (h ? c_hi : c_lo)) {
+          T* o = out + (long long)(m + (h ? d_hi : d_lo) + sb * PIX) * N + col;
+#pragma unroll
+          for (int j = 0; j < NF; ++j) {
+            const float v = fmaxf(acc[i][j][q] * args.acc_scale + args.bias[j * 16 + col], 0.f);
+            st_out<P>(o + j * 16, v, args.out_s8);
+          }
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) acc[i][j] = part[i][j];
+    lds_barrier();
+    if (more) {
+      store_a();
+      lds_barrier();
+    }
+  }
+}
+
 // FP32 fc1: h = ReLU((part_0 + part_1 + ... in slice order) * scale + b)
 __global__ void fc1_reduce_kernel(long long M, const float* __restrict__ part, const float* __restrict__ bias,
                                   float scale, float* __restrict__ out) {
@@ -486,8 +655,8 @@ __global__ void item_desc_kernel(long long item_begin, long long n_items, const 
 }
 
 template <int P>
-void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V, float* q0,
-              hipStream_t s, hipEvent_t* ev) {
+void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, const ChunkGroups& cg, void* ws, float* V,
+              float* q0, hipStream_t s, hipEvent_t* ev) {
   typedef typename PT<P>::T T;
   T* x1 = reinterpret_cast<T*>(ws);
   T* x2 = x1 + n * 12800;
@@ -508,7 +677,17 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, void* ws, flo
   if (ev) (void)hipEventRecord(ev[0], s);
   a.in_s8 = q.ascale[0];
   a.M = n * 400; a.in = nullptr; a.w = wp(0); a.bias = q.b[0]; a.acc_scale = accs(0); a.out_s8 = outs(0); a.out = x1;
-  run_layer<0, P>(a, s);
+  // (the group kernel indexes rows and output rows in 32 bits: chunks of up
+  // to 5 M stacks; a larger chunk runs conv1 stack by stack, same results)
+  if (cg.n > 0 && n * 400 + kBM < (1LL << 31)) {
+    a.M = (long long)cg.n * 400;
+    a.groups = cg.groups;
+    a.n_groups = cg.n;
+    a.item_base = cg.item_base;
+    hipLaunchKernelGGL((conv1_groups_kernel<P>), dim3((unsigned)((a.M + kBM - 1) / kBM)), dim3(kThreads), 0, s, a);
+  } else {
+    run_layer<0, P>(a, s);
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
   a.M = n * 81; a.in = x1; a.w = wp(1); a.bias = q.b[1]; a.acc_scale = accs(1); a.out_s8 = outs(1); a.out = x2;
   run_layer<1, P>(a, s);
@@ -571,10 +750,15 @@ void launch_item_desc(long long item_begin, long long n_items, const Seg* segs, 
 
 void launch_qnet(int prec, const QnetDev& q, const ItemDesc* desc, long long n, void* ws, float* V,
                  float* q0, hipStream_t s, hipEvent_t* ev) {
+  launch_qnet_groups(prec, q, desc, n, ChunkGroups{nullptr, 0, 0}, ws, V, q0, s, ev);
+}
+
+void launch_qnet_groups(int prec, const QnetDev& q, const ItemDesc* desc, long long n, const ChunkGroups& cg,
+                        void* ws, float* V, float* q0, hipStream_t s, hipEvent_t* ev) {
   if (n <= 0) return;
-  if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, ws, V, q0, s, ev);
-  else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, ws, V, q0, s, ev);
-  else run_qnet<P_FP8>(q, desc, n, ws, V, q0, s, ev);
+  if (prec == P_FP32) run_qnet<P_FP32>(q, desc, n, cg, ws, V, q0, s, ev);
+  else if (prec == P_BF16) run_qnet<P_BF16>(q, desc, n, cg, ws, V, q0, s, ev);
+  else run_qnet<P_FP8>(q, desc, n, cg, ws, V, q0, s, ev);
 }
 
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h,

@@ -115,18 +115,12 @@ static void check_plan(const Plan& p, int n, const std::vector<int32_t>& dv, con
     CHECK(seen[3 * r + 2] == (corrected || d == 0), "root segment of root %d", r);
   }
   if (!corr_fp32) CHECK(p.tail_item0 == p.n_items && p.tail_chunks.empty(), "no tail expected");
-  // ---- tail chunks
-  long long t = p.tail_item0;
-  for (const auto& tc : p.tail_chunks) {
-    CHECK(tc.first == t && tc.second > tc.first && tc.second - tc.first <= std::max(1LL, tail_items), "tail chunk");
-    CHECK(tc.second - tc.first <= p.tail_chunk, "tail_chunk");
-    t = tc.second;
-  }
-  CHECK(t == p.n_items, "tail chunks cover the tail");
-  // ---- sibling groups: cover [0, tail_item0), each inside one segment, whole sibling sets
+  // ---- sibling groups: cover [0, n_items), each inside one segment, whole sibling sets
   long long g_item = 0;
   size_t si = 0;
+  int main_groups = -1;
   for (const FusedGroup& g : p.groups) {
+    if (g.item0 == p.tail_item0 && main_groups < 0) main_groups = (int)(&g - p.groups.data());
     CHECK(g.item0 == g_item && g.count >= 1, "groups are contiguous");
     while (si < p.segs.size() && p.segs[si].item0 + (p.segs[si].kind == 2 ? 1 : p.segs[si].kind == 1 ? av[p.segs[si].root] : p.roots[p.segs[si].root].lcnt[dv[p.segs[si].root]]) <= g.item0) ++si;
     CHECK(si < p.segs.size(), "group past the segments");
@@ -137,21 +131,28 @@ static void check_plan(const Plan& p, int n, const std::vector<int32_t>& dv, con
           (long long)g.item0, sg.kind, A);
     g_item += g.count;
   }
-  CHECK(g_item == p.tail_item0, "groups cover the main items: %lld vs %lld", g_item, p.tail_item0);
-  // ---- chunks: whole groups, bounded size
-  int gi = 0;
+  CHECK(g_item == p.n_items, "groups cover the items: %lld vs %lld", g_item, p.n_items);
+  if (main_groups < 0) main_groups = (int)p.groups.size();
+  // ---- chunks, then tail chunks: whole groups, bounded size
   long long maxg = 1;
   for (const auto& g : p.groups) maxg = std::max<long long>(maxg, g.count);
-  for (const auto& ch : p.chunks) {
-    CHECK(ch.g0 == gi && ch.g1 > ch.g0 && ch.g1 <= (int)p.groups.size(), "chunk groups");
-    CHECK(ch.i0 == p.groups[ch.g0].item0, "chunk start");
-    long long items = 0;
-    for (int g = ch.g0; g < ch.g1; ++g) items += p.groups[g].count;
-    CHECK(ch.i1 - ch.i0 == items && items <= std::max(std::max(1LL, chunk_items), maxg) && items <= p.chunk,
-          "chunk of %lld items", items);
-    gi = ch.g1;
-  }
-  CHECK(gi == (int)p.groups.size(), "chunks cover the groups");
+  auto check_chunks = [&](const std::vector<Plan::Chunk>& chunks, int g_from, int g_to, long long want,
+                          long long most, const char* what) {
+    int gi = g_from;
+    for (const auto& ch : chunks) {
+      CHECK(ch.g0 == gi && ch.g1 > ch.g0 && ch.g1 <= g_to, "%s groups", what);
+      CHECK(ch.i0 == p.groups[ch.g0].item0, "%s start", what);
+      long long items = 0;
+      for (int g = ch.g0; g < ch.g1; ++g) items += p.groups[g].count;
+      CHECK(ch.i1 - ch.i0 == items && items <= std::max(std::max(1LL, want), maxg) && items <= most,
+            "%s of %lld items", what, items);
+      gi = ch.g1;
+    }
+    CHECK(gi == g_to, "%s cover their groups", what);
+  };
+  check_chunks(p.chunks, 0, main_groups, chunk_items, p.chunk, "chunk");
+  check_chunks(p.tail_chunks, main_groups, (int)p.groups.size(), tail_items, p.tail_chunk, "tail chunk");
+  if (!p.tail_chunks.empty()) CHECK(p.tail_chunks.front().i0 == p.tail_item0, "the tail chunks start at tail_item0");
   // ---- arena layout: aligned, disjoint, inside total, large enough
   std::vector<std::pair<size_t, size_t>> reg;   // (offset, bytes needed)
   auto add = [&](size_t off, size_t bytes) { if (bytes) reg.emplace_back(off, bytes); };

@@ -76,6 +76,65 @@ def test_qnet_fp32_matches_oracle(lib, setup):
         assert (err <= bound).all(), (err / np.abs(want).max(axis=1)).max()
 
 
+def _sibling_stacks(world, seed, A, n_parents):
+    """The A children of n_parents roots: stacks that share channels 0..2."""
+    from oracle import env as E
+    pos, st = W.roots(seed, n_parents)
+    return np.stack([E.step(pos[r], st[r], a, world.delta, world.vel)[1]
+                     for r in range(n_parents) for a in range(A)])
+
+
+def test_fp32_sibling_groups_match_oracle(lib, setup):
+    """FP32 conv1 by sibling groups (channels 0..2 summed once per group, each
+    sibling's channel 3 added to a copy): groups of 18, 6, 4 and a ragged
+    last group against the FP64 oracle at the FP32 bar, and bit for bit equal
+    to the same stacks evaluated one by one and with the grouping off."""
+    ctx, world, _ = setup
+    ctx.set_precision(lib.FP32)
+    try:
+        for A, npar, group in ((18, 3, 18), (6, 5, 6), (4, 7, 4), (5, 3, 4)):
+            x = _sibling_stacks(world, 3300 + A, A, npar)
+            if group != A:      # groups of 4 over parents of 5 children: keep whole parents per group
+                x = np.concatenate([x[r * A:r * A + group] for r in range(npar)] + [x[:1]])
+            got = ctx.debug_qnet_siblings(x, 18, group)
+            want = Q.qvalues(x, world.w64, 18)
+            err = np.abs(got - want).max(axis=1)
+            assert (err <= RTOL * np.abs(want).max(axis=1) + 1e-6).all(), (A, (err / np.abs(want).max(axis=1)).max())
+            np.testing.assert_array_equal(got, ctx.debug_qnet(x, 18))
+            ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 0)
+            np.testing.assert_array_equal(got, ctx.debug_qnet_siblings(x, 18, group))
+            ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
+    finally:
+        ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
+
+
+def test_conv1_groups_searches_bit_identical(lib, setup):
+    """Whole searches with conv1 by sibling groups equal those with conv1 per
+    stack, bit for bit: FP32 (every layer-path chunk), BF16 (its FP32
+    correction evaluations, groups of A depth-1 nodes and single roots),
+    on a mixed batch with A in {4, 6, 18}, d in {1, 2, 3}, in small chunks
+    so that groups end at chunk edges."""
+    ctx, _, _ = setup
+    A, d = W.mixed_shapes(1006, 120, (4, 6, 18), (1, 2, 3))
+    pos, st = W.roots(1006, 120)
+    corr = lib.correction(True, 1.0)
+    chunk = ctx.get_tuning(lib.TUNE_LAYER_CHUNK)
+    try:
+        ctx.set_tuning(lib.TUNE_LAYER_CHUNK, 1000)
+        for prec in (lib.FP32, lib.BF16):
+            ctx.set_precision(prec)
+            out = []
+            for knob in (1, 0):
+                ctx.set_tuning(lib.TUNE_CONV1_GROUPS, knob)
+                out.append(ctx.search_batch(pos, st, d, A, GAMMA, corr))
+            assert np.array_equal(out[0][0], out[1][0]), prec
+            assert np.array_equal(out[0][1], out[1][1]), prec
+    finally:
+        ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
+        ctx.set_tuning(lib.TUNE_LAYER_CHUNK, chunk)
+        ctx.set_precision(lib.FP32)
+
+
 @pytest.mark.parametrize("corr_on,c", [(True, 1.0), (False, 1.0), (True, 0.0), (True, 2.5)])
 def test_c1_end_to_end(lib, setup, corr_on, c):
     """64 roots, A=4, d=2 (the small configuration), FP32."""
