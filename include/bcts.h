@@ -253,11 +253,16 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          summed the same way by both, so the results are
  *                          the same up to FP32 addition order.
  *   BCTS_TUNE_CONV1_GROUPS layer-by-layer path (FP32, the FP32 correction
- *                          evaluations, BCTS_TUNE_FUSED = 0): 1 (default) =
- *                          conv1 sums the channels a sibling group's stacks
- *                          share (0..2) once per group and adds each
- *                          sibling's channel 3 to that partial sum, 0 = every
- *                          stack alone.  Same results, bit for bit.        */
+ *                          evaluations, BCTS_TUNE_FUSED = 0): conv1 by
+ *                          sibling groups -- the channels a group's stacks
+ *                          share (0..2) summed once per group, each
+ *                          sibling's channel 3 added to that partial sum --
+ *                          or stack by stack.  2 = always by groups, 0 =
+ *                          never, 1 (default) = per chunk, by groups when
+ *                          the chunk holds enough groups to fill the GPU
+ *                          (the group kernel's workgroups run longer: a
+ *                          lone small request finishes sooner stack by
+ *                          stack).  Same results, bit for bit.             */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,

@@ -56,7 +56,7 @@ struct bcts_ctx {
   long long fused_chunk_items = 262144; // fused path (BF16 / FP8)
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
   bool fp8_k128 = true;                 // FP8 conv2 / conv3 on the K = 128 matrix instruction
-  bool conv1_groups = true;             // layer path: conv1's shared channels once per sibling group
+  int conv1_groups = 1;                 // layer path, conv1 by sibling groups: 0 never, 1 when faster, 2 always
   bool fused = true;
   bool corr_fp32 = true;                // root / depth-1 evals of corrected roots in FP32
   int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
@@ -345,6 +345,21 @@ bcts_status enqueue_level(bcts_ctx* c, const Plan& p, char* A, int k, const int3
   return BCTS_OK;
 }
 
+// conv1 of a layer-path chunk by sibling groups (true) or stack by stack.
+// Workgroups of 128 pixel rows, about kSlots resident at once: the group
+// kernel runs 6 + 2 x (group size) stages per workgroup, the per-stack
+// kernel 8; the time of a launch is taken as the larger of its total stages
+// over the slots and one workgroup's stages.  A lone small request is then
+// latency-bound and runs per stack; a chunk of many groups runs by groups.
+bool conv1_by_groups(const bcts_ctx* c, const Plan::Chunk& ch) {
+  if (c->conv1_groups != 1) return c->conv1_groups == 2;
+  constexpr double kSlots = 256.0 * 5.0;            // CUs x resident workgroups of the FP32 kernels
+  constexpr double kTilesPerStack = 400.0 / 128.0;  // workgroups per stack (or per group)
+  const double per_stack = std::max(8.0 * kTilesPerStack * (double)(ch.i1 - ch.i0) / kSlots, 8.0);
+  const double grouped = std::max(kTilesPerStack * (double)ch.group_stages / kSlots, 6.0 + 2.0 * ch.max_group);
+  return grouped < per_stack;
+}
+
 // Q-network chunk ci of the plan.  With `cev` (6 events) its launches are
 // bracketed.
 bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* desc, char* ws, const FrameBases& fb,
@@ -359,7 +374,7 @@ bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* de
   const long long cnt = ch.i1 - ch.i0;
   launch_item_desc(ch.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
   if (!p.fused) {
-    const ChunkGroups cg{groups + ch.g0, c->conv1_groups ? ch.g1 - ch.g0 : 0, ch.i0};
+    const ChunkGroups cg{groups + ch.g0, conv1_by_groups(c, ch) ? ch.g1 - ch.g0 : 0, ch.i0};
     launch_qnet_groups(c->prec, c->q, desc, cnt, cg, ws, V + ch.i0, q0, s, cev);
     return BCTS_OK;
   }
@@ -407,7 +422,7 @@ bcts_status enqueue_tail(bcts_ctx* c, const Plan& p, char* A, ItemDesc* desc, ch
   for (const auto& tc : p.tail_chunks) {
     const long long cnt = tc.i1 - tc.i0;
     launch_item_desc(tc.i0, cnt, reinterpret_cast<const Seg*>(A + p.o_segs), (int)p.segs.size(), roots, fb, desc, s);
-    const ChunkGroups cg{groups + tc.g0, c->conv1_groups ? tc.g1 - tc.g0 : 0, tc.i0};
+    const ChunkGroups cg{groups + tc.g0, conv1_by_groups(c, tc) ? tc.g1 - tc.g0 : 0, tc.i0};
     launch_qnet_groups(P_FP32, c->q, desc, cnt, cg, ws, V + tc.i0, q0, s, nullptr);
   }
   return BCTS_OK;
@@ -1595,22 +1610,11 @@ bcts_status debug_qnet_impl(bcts_ctx* c, int32_t n, const uint8_t* stacks, int32
     // regroup the one-item root groups into sibling groups, chunks of whole groups
     p.groups.clear();
     for (long long i = 0; i < n; i += group) p.groups.push_back(FusedGroup{i, (int)std::min<long long>(group, n - i), 0});
-    const long long target = std::max(1LL, p.fused ? c->fused_chunk_items : c->chunk_items);
     p.chunks.clear();
-    int g = 0;
-    while (g < (int)p.groups.size()) {
-      Plan::Chunk ch;
-      ch.g0 = g;
-      ch.i0 = p.groups[g].item0;
-      long long items = 0;
-      while (g < (int)p.groups.size() && (items == 0 || items + p.groups[g].count <= target)) {
-        items += p.groups[g].count;
-        ++g;
-      }
-      ch.g1 = g;
-      ch.i1 = ch.i0 + items;
-      p.chunks.push_back(ch);
-    }
+    long long most = 1;
+    make_chunks(p, 0, (int)p.groups.size(), p.fused ? c->fused_chunk_items : c->chunk_items, p.chunks, &most);
+    if (most > p.chunk)       // the workspace was laid out for chunks of p.chunk items
+      return fail(c, BCTS_E_INVAL, "group of %d exceeds the chunk size of %lld stacks", group, p.chunk);
   }
   if ((st = ensure_arena(c, p.total)) != BCTS_OK) return st;
   hipStream_t s = c->stream;
@@ -1780,7 +1784,8 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
       c->corr_fp32 = value != 0;
       return BCTS_OK;
     case BCTS_TUNE_CONV1_GROUPS:
-      c->conv1_groups = value != 0;
+      if (value < 0 || value > 2) return fail(c, BCTS_E_INVAL, "conv1 grouping must be 0, 1 or 2");
+      c->conv1_groups = (int)value;
       return BCTS_OK;
     default:
       return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
@@ -1797,7 +1802,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_CORR_FP32: *value = c->corr_fp32 ? 1 : 0; return BCTS_OK;
     case BCTS_TUNE_MLP_CROSSOVER: *value = c->mlp_crossover; return BCTS_OK;
     case BCTS_TUNE_FP8_K128: *value = c->fp8_k128 ? 1 : 0; return BCTS_OK;
-    case BCTS_TUNE_CONV1_GROUPS: *value = c->conv1_groups ? 1 : 0; return BCTS_OK;
+    case BCTS_TUNE_CONV1_GROUPS: *value = c->conv1_groups; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }

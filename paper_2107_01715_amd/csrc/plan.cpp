@@ -80,6 +80,28 @@ size_t fused_workspace_bytes(long long chunk, int prec) {
   return fused_x3_bytes(chunk, prec) + (size_t)chunk * 512 * el + 256;
 }
 
+void make_chunks(const Plan& p, int g, int g_end, long long target, std::vector<Plan::Chunk>& out, long long* most) {
+  target = std::max(1LL, target);
+  while (g < g_end) {
+    Plan::Chunk ch;
+    ch.g0 = g;
+    ch.i0 = p.groups[g].item0;
+    ch.max_group = 0;
+    ch.group_stages = 0;
+    long long items = 0;
+    while (g < g_end && (items == 0 || items + p.groups[g].count <= target)) {
+      items += p.groups[g].count;
+      ch.max_group = std::max(ch.max_group, p.groups[g].count);
+      ch.group_stages += 6 + 2LL * p.groups[g].count;
+      ++g;
+    }
+    ch.g1 = g;
+    ch.i1 = ch.i0 + items;
+    *most = std::max(*most, items);
+    out.push_back(ch);
+  }
+}
+
 void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gamma,
                const bcts_correction& corr, int q_stride, long long chunk_items, int prec,
                bool host_io, bool fused, int beam, bool corr_fp32, long long tail_chunk_items) {
@@ -187,27 +209,9 @@ void make_plan(Plan& p, int n, const int32_t* depth, const int32_t* A, float gam
     for (long long j = 0; j < cnt; j += gsz) p.groups.push_back(FusedGroup{sg.item0 + j, gsz, 0});
   }
   if (main_segs == p.segs.size()) main_groups = (int)p.groups.size();
-  // chunks of whole groups, up to `target` items (or one group if larger)
-  auto chunk_groups = [&](int g, int g_end, long long target, std::vector<Plan::Chunk>& out, long long* most) {
-    target = std::max(1LL, target);
-    while (g < g_end) {
-      Plan::Chunk ch;
-      ch.g0 = g;
-      ch.i0 = p.groups[g].item0;
-      long long items = 0;
-      while (g < g_end && (items == 0 || items + p.groups[g].count <= target)) {
-        items += p.groups[g].count;
-        ++g;
-      }
-      ch.g1 = g;
-      ch.i1 = ch.i0 + items;
-      *most = std::max(*most, items);
-      out.push_back(ch);
-    }
-  };
   p.chunk = 1;
-  chunk_groups(0, main_groups, chunk_items, p.chunks, &p.chunk);
-  chunk_groups(main_groups, (int)p.groups.size(), tail_chunk_items, p.tail_chunks, &p.tail_chunk);
+  make_chunks(p, 0, main_groups, chunk_items, p.chunks, &p.chunk);
+  make_chunks(p, main_groups, (int)p.groups.size(), tail_chunk_items, p.tail_chunks, &p.tail_chunk);
 
   // arena layout
   size_t o = 0;

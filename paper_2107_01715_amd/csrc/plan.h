@@ -53,7 +53,10 @@ struct Plan {
   long long chunk = 0;                 // max items of a chunk
   bool fused = false;                  // conv stack fused per sibling group
   std::vector<FusedGroup> groups;      // sibling groups in item order (main items, then the tail's)
-  struct Chunk { int g0, g1; long long i0, i1; };
+  // A chunk: groups [g0, g1), items [i0, i1); its largest group and the sum
+  // over its groups of (6 + 2 x group size), the conv1 stages of the group
+  // kernel per 128 pixel rows
+  struct Chunk { int g0, g1; long long i0, i1; int max_group; long long group_stages; };
   std::vector<Chunk> chunks;           // whole groups of the main items, ~chunk_items items each
   // The correction's own Q-network inputs (the root and depth-1 evaluations
   // of corrected roots) can run in FP32 whatever the leaf precision: they
@@ -78,6 +81,11 @@ struct Plan {
   size_t search_bytes() const { return o_desc; }
   size_t shared_bytes() const { return total - o_desc; }
 };
+
+// Chunks of whole groups p.groups[g0, g1), up to `target` items each (one
+// group alone if it is larger), appended to `out`; *most is raised to the
+// largest chunk's items.
+void make_chunks(const Plan& p, int g0, int g1, long long target, std::vector<Plan::Chunk>& out, long long* most);
 
 
 // Build the plan: node counts, eval segments and the arena layout.

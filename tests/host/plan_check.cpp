@@ -142,8 +142,14 @@ static void check_plan(const Plan& p, int n, const std::vector<int32_t>& dv, con
     for (const auto& ch : chunks) {
       CHECK(ch.g0 == gi && ch.g1 > ch.g0 && ch.g1 <= g_to, "%s groups", what);
       CHECK(ch.i0 == p.groups[ch.g0].item0, "%s start", what);
-      long long items = 0;
-      for (int g = ch.g0; g < ch.g1; ++g) items += p.groups[g].count;
+      long long items = 0, stages = 0;
+      int most_g = 0;
+      for (int g = ch.g0; g < ch.g1; ++g) {
+        items += p.groups[g].count;
+        stages += 6 + 2LL * p.groups[g].count;
+        most_g = std::max(most_g, p.groups[g].count);
+      }
+      CHECK(ch.max_group == most_g && ch.group_stages == stages, "%s group statistics", what);
       CHECK(ch.i1 - ch.i0 == items && items <= std::max(std::max(1LL, want), maxg) && items <= most,
             "%s of %lld items", what, items);
       gi = ch.g1;

@@ -88,10 +88,13 @@ def test_fp32_sibling_groups_match_oracle(lib, setup):
     """FP32 conv1 by sibling groups (channels 0..2 summed once per group, each
     sibling's channel 3 added to a copy): groups of 18, 6, 4 and a ragged
     last group against the FP64 oracle at the FP32 bar, and bit for bit equal
-    to the same stacks evaluated one by one and with the grouping off."""
+    to the same stacks evaluated one by one and with the grouping off.  (At
+    these sizes the default choice would run conv1 per stack: the grouping is
+    forced on.)"""
     ctx, world, _ = setup
     ctx.set_precision(lib.FP32)
     try:
+        ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 2)
         for A, npar, group in ((18, 3, 18), (6, 5, 6), (4, 7, 4), (5, 3, 4)):
             x = _sibling_stacks(world, 3300 + A, A, npar)
             if group != A:      # groups of 4 over parents of 5 children: keep whole parents per group
@@ -103,7 +106,7 @@ def test_fp32_sibling_groups_match_oracle(lib, setup):
             np.testing.assert_array_equal(got, ctx.debug_qnet(x, 18))
             ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 0)
             np.testing.assert_array_equal(got, ctx.debug_qnet_siblings(x, 18, group))
-            ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
+            ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 2)
     finally:
         ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
 
@@ -113,7 +116,8 @@ def test_conv1_groups_searches_bit_identical(lib, setup):
     stack, bit for bit: FP32 (every layer-path chunk), BF16 (its FP32
     correction evaluations, groups of A depth-1 nodes and single roots),
     on a mixed batch with A in {4, 6, 18}, d in {1, 2, 3}, in small chunks
-    so that groups end at chunk edges."""
+    so that groups end at chunk edges; the default per-chunk choice (which
+    here takes both kernels) agrees with both."""
     ctx, _, _ = setup
     A, d = W.mixed_shapes(1006, 120, (4, 6, 18), (1, 2, 3))
     pos, st = W.roots(1006, 120)
@@ -124,11 +128,15 @@ def test_conv1_groups_searches_bit_identical(lib, setup):
         for prec in (lib.FP32, lib.BF16):
             ctx.set_precision(prec)
             out = []
-            for knob in (1, 0):
+            for knob in (2, 0, 1):
                 ctx.set_tuning(lib.TUNE_CONV1_GROUPS, knob)
                 out.append(ctx.search_batch(pos, st, d, A, GAMMA, corr))
-            assert np.array_equal(out[0][0], out[1][0]), prec
-            assert np.array_equal(out[0][1], out[1][1]), prec
+            for k in (1, 2):
+                assert np.array_equal(out[0][0], out[k][0]), (prec, k)
+                assert np.array_equal(out[0][1], out[k][1]), (prec, k)
+        with pytest.raises(lib.BctsError) as e:
+            ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 3)
+        assert e.value.status == lib.E_INVAL
     finally:
         ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
         ctx.set_tuning(lib.TUNE_LAYER_CHUNK, chunk)
