@@ -438,7 +438,9 @@ bcts_status bcts_debug_qnet_siblings(bcts_ctx* ctx, int32_t n, const uint8_t* st
  *   levels 1..6, out[16] Q-network items, out[17] expanded nodes, out[18] 1 if
  *   the fused conv kernel ran (its time is then in out[4]; out[5..6] are 0),
  *   out[19] ms of the FP32 correction evaluations (BCTS_TUNE_CORR_FP32;
- *   included in out[1], not in out[4..8]).
+ *   included in out[1], not in out[4..8]), out[20] chunks of the
+ *   layer-by-layer path whose conv1 ran by sibling groups
+ *   (BCTS_TUNE_CONV1_GROUPS).
  * A graph replay fills only out[3] (ms per replay).  out has 24 doubles.    */
 bcts_status bcts_set_timing(bcts_ctx* ctx, int32_t enabled);
 bcts_status bcts_get_timing(bcts_ctx* ctx, double* out24);

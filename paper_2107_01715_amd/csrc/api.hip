@@ -99,7 +99,7 @@ struct bcts_ctx {
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> tev;      // [start, level 1..maxd, chunk x 6, qnet end, end]
-  int t_maxd = 0, t_chunks = 0;
+  int t_maxd = 0, t_chunks = 0, t_conv1_groups = 0;
   bool t_fused = false, t_tail = false;
   long long t_items = 0, t_nodes = 0;
   double t_ms[24] = {0};
@@ -475,6 +475,9 @@ bcts_status enqueue_search_at(bcts_ctx* c, const Plan& p, char* A, const int32_t
     c->t_fused = p.fused;
     c->t_items = p.n_items;
     c->t_tail = !p.tail_chunks.empty();
+    c->t_conv1_groups = 0;
+    if (!p.fused)
+      for (const auto& ch : p.chunks) c->t_conv1_groups += conv1_by_groups(c, ch) ? 1 : 0;
     c->t_nodes = 0;
     for (int k = 1; k <= p.maxd; ++k) c->t_nodes += p.lvl_count[k];
     HIPCHECK(c, hipEventRecord(ev[0], s));
@@ -503,7 +506,8 @@ bcts_status enqueue_search(bcts_ctx* c, const Plan& p, const int32_t* d_pos, con
 // [0] expansion, [1] Q-network, [2] backup + correction, [3] total (ms);
 // [4..8] conv1, conv2, conv3, fc1, fc2 summed over chunks (ms); [9] chunks;
 // [10..15] expansion of levels 1..6 (ms); [16] eval items; [17] new nodes;
-// [18] fused kernel ran; [19] FP32 correction evaluations (ms).
+// [18] fused kernel ran; [19] FP32 correction evaluations (ms); [20] chunks
+// of the layer path whose conv1 ran by sibling groups.
 // Events: [0] start, [k] after level k, then 6 per chunk, 2 around the FP32
 // correction evaluations, the Q-network end and the search end.
 bcts_status collect_timing(bcts_ctx* c) {
@@ -529,6 +533,7 @@ bcts_status collect_timing(bcts_ctx* c) {
   c->t_ms[17] = (double)c->t_nodes;
   c->t_ms[18] = c->t_fused ? 1.0 : 0.0;
   c->t_ms[19] = c->t_tail ? el(tail0, tail0 + 1) : 0.0;
+  c->t_ms[20] = c->t_conv1_groups;
   return BCTS_OK;
 }
 
