@@ -419,6 +419,17 @@ def run_mlp(args):
             ctx.set_tuning(bcts.TUNE_MLP_CROSSOVER, 0)
             times = {k: v for k, v in row.items() if k.startswith("host_levels_")}
             row["best_crossover_depth"] = int(min(times, key=times.get).split("_")[2])
+            # the whole search on the host CPU (the paper's CPU BFS), one core
+            ctx.set_tuning(bcts.TUNE_MLP_HOST, 1)
+            cpu = []
+            for i in range(reps if A ** d < 10 ** 4 else 3):
+                t0 = time.perf_counter()
+                ctx.mlp_search(st_h[i % 64:i % 64 + 1], d, A, GAMMA, corr)
+                cpu.append(time.perf_counter() - t0)
+            ctx.set_tuning(bcts.TUNE_MLP_HOST, 0)
+            row["cpu_bfs_ms"] = float(np.median(cpu)) * 1e3
+            row["fastest"] = ("cpu_bfs" if row["cpu_bfs_ms"] < min(times.values())
+                              else f"host_levels_{row['best_crossover_depth']}")
             crossover.append(row)
         ctx.close()
         print(f"# mlp A={A}: {[(r['depth'], round(r['gpu_ms_per_search'], 4)) for r in rows if r['A'] == A]}",
@@ -441,7 +452,8 @@ def run_mlp(args):
         "crossover": {"rows": crossover,
                       "what": "median ms per host-buffer search of one root (state in, action and root vector "
                               "out, PCIe included) with levels 1..k expanded on the host CPU and the rest on the "
-                              "GPU; best_crossover_depth = the fastest k"},
+                              "GPU; best_crossover_depth = the fastest k; cpu_bfs_ms = the whole search on one "
+                              "host core (the CPU BFS, the same bits); fastest = the fastest of all"},
         "cpu_baseline": {"kind": "oracle", "cores": 1, "rows": cpu_rows,
                          "sample": "FP64 depth-first search of one root on one host core, averaged over up to "
                                    "16 roots within 2 s per depth"} if cpu_rows else None,

@@ -262,7 +262,18 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          the chunk holds enough groups to fill the GPU
  *                          (the group kernel's workgroups run longer: a
  *                          lone small request finishes sooner stack by
- *                          stack).  Same results, bit for bit.             */
+ *                          stack).  Same results, bit for bit.
+ *   BCTS_TUNE_MLP_HOST     forward-model world, host-buffer searches
+ *                          (bcts_mlp_search): 1 = the whole search on the
+ *                          host CPU -- every level, the leaves' head, the
+ *                          backup and the correction -- the CPU BFS of the
+ *                          Sec. 4.1 runtime study; the GPU is not used.  The
+ *                          device kernels' FP32 arithmetic in their order:
+ *                          the same bits as the GPU search.  2 = the host
+ *                          for small trees (at most 32 + 9 d nodes per
+ *                          root, where one host core beats a host-buffer
+ *                          GPU search), the GPU otherwise.  0 (default) =
+ *                          the GPU (with BCTS_TUNE_MLP_CROSSOVER).          */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
@@ -271,7 +282,8 @@ typedef enum {
   BCTS_TUNE_CORR_FP32 = 4,
   BCTS_TUNE_MLP_CROSSOVER = 5,
   BCTS_TUNE_FP8_K128 = 6,
-  BCTS_TUNE_CONV1_GROUPS = 7
+  BCTS_TUNE_CONV1_GROUPS = 7,
+  BCTS_TUNE_MLP_HOST = 8
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);

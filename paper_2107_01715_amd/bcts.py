@@ -48,6 +48,7 @@ EXPORTS = (
 TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32, TUNE_MLP_CROSSOVER = 0, 1, 2, 3, 4, 5
 TUNE_FP8_K128 = 6
 TUNE_CONV1_GROUPS = 7
+TUNE_MLP_HOST = 8
 
 
 class EnvParamsC(ctypes.Structure):

@@ -117,6 +117,7 @@ struct bcts_ctx {
   bool mlp_set = false;
   MlpHost mlp_h{};
   int mlp_crossover = 0;               // levels a host-buffer search expands on the CPU
+  int mlp_host = 0;                     // host-buffer searches wholly on the CPU: 0 never, 1 always, 2 small trees
 };
 
 namespace {
@@ -1788,6 +1789,10 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
     case BCTS_TUNE_CORR_FP32:
       c->corr_fp32 = value != 0;
       return BCTS_OK;
+    case BCTS_TUNE_MLP_HOST:
+      if (value < 0 || value > 2) return fail(c, BCTS_E_INVAL, "host search mode must be 0, 1 or 2");
+      c->mlp_host = (int)value;
+      return BCTS_OK;
     case BCTS_TUNE_CONV1_GROUPS:
       if (value < 0 || value > 2) return fail(c, BCTS_E_INVAL, "conv1 grouping must be 0, 1 or 2");
       c->conv1_groups = (int)value;
@@ -1808,6 +1813,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_MLP_CROSSOVER: *value = c->mlp_crossover; return BCTS_OK;
     case BCTS_TUNE_FP8_K128: *value = c->fp8_k128 ? 1 : 0; return BCTS_OK;
     case BCTS_TUNE_CONV1_GROUPS: *value = c->conv1_groups; return BCTS_OK;
+    case BCTS_TUNE_MLP_HOST: *value = c->mlp_host; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }
@@ -2084,6 +2090,24 @@ bcts_status bcts_mlp_search(bcts_ctx* c, int32_t n_roots, const float* states, i
   if (!states || !out_action || !out_q) return fail(c, BCTS_E_INVAL, "NULL pointer");
   for (long long i = 0; i < (long long)n_roots * 100; ++i)
     if (!std::isfinite(states[i])) return fail(c, BCTS_E_INVAL, "state value %lld is not finite", i);
+  // Mode 2 takes the host for small trees: one host node (a child's model
+  // step and head) costs about 1.4 us on one core, a host-buffer search on
+  // the GPU about 45 us plus 12.5 us per level (PCIe both ways, a launch per
+  // level), so the host is the faster device below 32 + 9 d nodes per root.
+  long long nodes = 0;
+  for (long long k = 1, cnt = 1; k <= depth; ++k) nodes += (cnt *= c->mlp.A);
+  if (c->mlp_host == 1 || (c->mlp_host == 2 && nodes <= 32 + 9LL * depth)) {
+    // the CPU BFS: every level, the leaves, the backup and the correction on
+    // the host, in the device kernels' arithmetic
+    double pe = 0.0, po = 0.0;
+    if (corr.enabled && depth >= 1) {
+      if (corr.mode == BCTS_CORR_EXACT_GEV) gev_coeffs(c->mlp.A, depth, &pe, &po);
+      else eq6_coeffs(c->mlp.A, depth, &pe, &po);
+    }
+    mlp_host_search(c->mlp_h, n_roots, states, depth, gamma, corr.enabled != 0, (float)pe, (float)po,
+                    corr.enabled ? corr.scale : 0.f, out_action, out_q);
+    return BCTS_OK;
+  }
   HIPCHECK(c, hipSetDevice(c->device));
   MlpPlan p;
   if ((st = mlp_plan(c, n_roots, depth, true, p)) != BCTS_OK) return st;

@@ -219,7 +219,8 @@ __global__ void __launch_bounds__(64) mlp_root_kernel(MlpDev m, int d, const flo
         for (int a = 0; a < A; ++a)
           if (a != pi) se += fabsf(dels[a]);
         const float de = se / (float)(A - 1);
-        const float shift = scale * gamma_d * (pen_e * de - pen_o * dobs);
+        // one rounding of pen_e d_e - pen_o d_o (the host search does the same)
+        const float shift = scale * gamma_d * fmaf(pen_e, de, -(pen_o * dobs));
         for (int a = 0; a < A; ++a)
           if (a != pi) outs[a] -= shift;
       }

@@ -6,6 +6,7 @@
 #include "mlp_host.h"
 
 #include <cmath>
+#include <vector>
 
 namespace bcts {
 namespace {
@@ -121,6 +122,71 @@ void mlp_host_level(const MlpHost& m, long long n, const float* ps, const float*
   static const bool fma = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
   if (fma) level_fma(m, n, ps, pret, gpow, os, oret, ov);
   else level_generic(m, n, ps, pret, gpow, os, oret, ov);
+}
+
+void mlp_host_search(const MlpHost& m, int n, const float* states, int d, float gamma, bool corr, float pen_e,
+                     float pen_o, float scale, int32_t* act, float* q) {
+  const int A = m.A;
+  const bool corr_on = corr && d >= 1;
+  const float gamma_d = (float)std::pow((double)gamma, d);
+  std::vector<float> ps(states, states + (size_t)n * kS), pr, ns, nr, nv, ret1, v1, qd;
+  long long cnt = n;
+  for (int k = 1; k <= d; ++k) {
+    cnt *= A;
+    const bool last = k == d;
+    ns.resize(last ? 0 : (size_t)cnt * kS);
+    nr.resize((size_t)cnt);
+    nv.resize(last || (k == 1 && corr_on) ? (size_t)cnt : 0);
+    mlp_host_level(m, cnt, ps.data(), k == 1 ? nullptr : pr.data(), (float)std::pow((double)gamma, (double)(k - 1)),
+                   last ? nullptr : ns.data(), nr.data(), nv.empty() ? nullptr : nv.data());
+    if (k == 1) {
+      ret1 = nr;
+      if (corr_on) v1 = nv;
+    }
+    if (last) {
+      const long long block = cnt / ((long long)n * A);     // leaves per (root, root action)
+      qd.assign((size_t)n * A, -INFINITY);
+      for (long long c = 0; c < cnt; ++c) {
+        float& b = qd[(size_t)(c / block)];
+        b = std::fmax(b, std::fmaf(gamma_d, nv[c], nr[c]));
+      }
+    }
+    ps.swap(ns);
+    pr.swap(nr);
+  }
+  std::vector<float> q0s(A), dels(A), outs(A);
+  for (int r = 0; r < n; ++r) {
+    const float* s = states + (size_t)r * kS;
+    for (int a = 0; a < A; ++a) {
+      float acc = m.bq[a];
+      for (int k = 0; k < kS; ++k) acc = std::fmaf(m.wqT[(size_t)k * A + a], s[k], acc);
+      q0s[a] = acc;
+      if (corr_on) dels[a] = std::fmaf(gamma, v1[(size_t)r * A + a], ret1[(size_t)r * A + a]) - acc;
+    }
+    if (d == 0) {
+      outs = q0s;
+    } else {
+      for (int a = 0; a < A; ++a) outs[a] = qd[(size_t)r * A + a];
+      if (corr_on) {
+        int pi = 0;
+        for (int a = 1; a < A; ++a)
+          if (q0s[a] > q0s[pi]) pi = a;
+        const float dobs = std::fabs(dels[pi]);
+        float se = 0.f;
+        for (int a = 0; a < A; ++a)
+          if (a != pi) se += std::fabs(dels[a]);
+        const float de = se / (float)(A - 1);
+        const float shift = scale * gamma_d * std::fmaf(pen_e, de, -(pen_o * dobs));
+        for (int a = 0; a < A; ++a)
+          if (a != pi) outs[a] -= shift;
+      }
+    }
+    int best = 0;
+    for (int a = 1; a < A; ++a)
+      if (outs[best] < outs[a]) best = a;
+    act[r] = best;
+    for (int a = 0; a < A; ++a) q[(size_t)r * A + a] = outs[a];
+  }
 }
 
 }  // namespace bcts

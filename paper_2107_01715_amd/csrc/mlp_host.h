@@ -4,6 +4,7 @@
 // there and moves to the GPU at a cross-over depth).  Pure C++, no HIP.
 #pragma once
 #include <stddef.h>
+#include <stdint.h>
 
 #include <vector>
 
@@ -32,5 +33,17 @@ void mlp_host_prepare(MlpHost& m, int A, const float* dev_blob);
 // return by one fused multiply-add), so the two devices give the same bits.
 void mlp_host_level(const MlpHost& m, long long n, const float* ps, const float* pret, float gpow, float* os,
                     float* oret, float* ov);
+
+// The whole search of n roots on the host: the CPU BFS of the Sec. 4.1
+// runtime study.  Levels 1..d as mlp_host_level; each leaf's value
+// r + gamma^d max_a Q(leaf, a); their maximum per (root, root action) block
+// (Eq. 1); the roots' Q0 = Wq s + bq; with `corr` the shift of Eq. 3 by
+// scale gamma^d B, B = pen_e d_e - pen_o d_o (Prop. 3.6: d_o = |delta of
+// pi_o|, d_e the mean |delta| of the other actions, delta_a = r_a +
+// gamma max Q(s_1^a) - Q0_a).  act[n] gets the argmax (lowest index), q[n][A]
+// the root vectors.  Every value is the device kernels' FP32 arithmetic in
+// their order, so the results are the GPU search's bits.
+void mlp_host_search(const MlpHost& m, int n, const float* states, int d, float gamma, bool corr, float pen_e,
+                     float pen_o, float scale, int32_t* act, float* q);
 
 }  // namespace bcts

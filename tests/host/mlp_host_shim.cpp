@@ -12,5 +12,9 @@ void shim_level(void* m, long long n, const float* ps, const float* pret, float 
                 float* ov) {
   bcts::mlp_host_level(*static_cast<bcts::MlpHost*>(m), n, ps, pret, gpow, os, oret, ov);
 }
+void shim_search(void* m, int n, const float* states, int d, float gamma, int corr, float pen_e, float pen_o,
+                 float scale, int32_t* act, float* q) {
+  bcts::mlp_host_search(*static_cast<bcts::MlpHost*>(m), n, states, d, gamma, corr != 0, pen_e, pen_o, scale, act, q);
+}
 void shim_free(void* m) { delete static_cast<bcts::MlpHost*>(m); }
 }

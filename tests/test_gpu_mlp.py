@@ -159,6 +159,30 @@ def test_crossover_equals_gpu_search(lib, model, crossover):
             check(q[r], int(act[r]), ref, f"A={A} d=5 crossover {crossover} root {r}")
 
 
+def test_cpu_bfs_equals_gpu_search(lib, model):
+    """The whole search on the host (the CPU BFS of the runtime study) gives
+    the GPU search's actions and root vectors bit for bit: every depth to 5
+    (4 at A = 10), both correction modes and none, 3 roots per call."""
+    ctx, A, _ = model
+    st = W.mlp_states(104, 3)
+    try:
+        for d in range(0, 6 if A == 2 else 5):
+            for corr in (lib.correction(True, 1.0), lib.correction(False, 0.0),
+                         lib.correction(True, 0.5, lib.CORR_EXACT_GEV)):
+                ctx.set_tuning(lib.TUNE_MLP_HOST, 0)
+                a0, q0 = ctx.mlp_search(st, d, A, GAMMA, corr)
+                for mode in (1, 2):                  # always on the host; the host for small trees
+                    ctx.set_tuning(lib.TUNE_MLP_HOST, mode)
+                    a1, q1 = ctx.mlp_search(st, d, A, GAMMA, corr)
+                    assert np.array_equal(a0, a1), (d, mode)
+                    assert np.array_equal(q0, q1), (d, mode, np.abs(q0 - q1).max())
+        with pytest.raises(lib.BctsError) as e:
+            ctx.set_tuning(lib.TUNE_MLP_HOST, 3)
+        assert e.value.status == lib.E_INVAL
+    finally:
+        ctx.set_tuning(lib.TUNE_MLP_HOST, 0)
+
+
 def test_crossover_argument(lib, model):
     ctx, _, _ = model
     with pytest.raises(lib.BctsError) as e:

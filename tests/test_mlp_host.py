@@ -1,8 +1,12 @@
-"""The host levels of the forward-model search (csrc/mlp_host.cpp, the CPU
-side of the CPU-to-GPU cross-over), built on their own with g++ and checked
-on the CPU against the FP64 oracle's model step: child states, rewards into
-returns (r + gamma^(k-1) discounting), and the head maximum at level 1, for
-A = 2 and 10 over two levels."""
+"""The host side of the forward-model search (csrc/mlp_host.cpp: the CPU
+levels of the CPU-to-GPU cross-over and the whole-search CPU BFS), built on
+its own with g++ and checked on the CPU against the FP64 oracle:
+* the levels against the oracle's model step: child states, rewards into
+  returns (r + gamma^(k-1) discounting), and the head maximum at level 1, for
+  A = 2 and 10 over two levels;
+* the whole search against ``oracle.mlp.search``: root vectors within 1e-5 of
+  the largest |Q| (1e-6 floor) and actions equal up to ties, A = 2 and 10,
+  depth 0..3 (0..5 at A = 2), with the Eq. 6 correction and without."""
 import ctypes
 import os
 import shutil
@@ -33,8 +37,18 @@ def host_lib(tmp_path_factory):
     lib.shim_create.argtypes = [ctypes.c_int, FP]
     lib.shim_level.restype = None
     lib.shim_level.argtypes = [ctypes.c_void_p, ctypes.c_longlong, FP, FP, ctypes.c_float, FP, FP, FP]
+    lib.shim_search.restype = None
+    lib.shim_search.argtypes = [ctypes.c_void_p, ctypes.c_int, FP, ctypes.c_int, ctypes.c_float, ctypes.c_int,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int32), FP]
     lib.shim_free.argtypes = [ctypes.c_void_p]
     return lib
+
+
+def _dev_blob(w):
+    l1 = w["l1.w"]
+    return np.concatenate([a.reshape(-1) for a in (
+        l1[:, :100], l1[:, 100:].T, w["l1.b"], w["l2.w"], w["l2.b"], w["l3.w"], w["l3.b"], w["out.w"], w["out.b"],
+        w["q.w"], w["q.b"])]).astype(np.float32)
 
 
 def _f(a):
@@ -48,11 +62,7 @@ def _p(a):
 @pytest.mark.parametrize("A", [2, 10])
 def test_host_levels_match_oracle_steps(host_lib, A):
     w = W.mlp_weights(11, A)
-    l1 = w["l1.w"]
-    dev_blob = np.concatenate([a.reshape(-1) for a in (
-        l1[:, :100], l1[:, 100:].T, w["l1.b"], w["l2.w"], w["l2.b"], w["l3.w"], w["l3.b"], w["out.w"], w["out.b"],
-        w["q.w"], w["q.b"])]).astype(np.float32)
-    m = host_lib.shim_create(A, _p(dev_blob))
+    m = host_lib.shim_create(A, _p(_dev_blob(w)))
     level = lambda *a: host_lib.shim_level(m, *a)  # noqa: E731
     w64 = M.prepare(w)
     n_roots, gamma = 3, 0.97
@@ -75,4 +85,32 @@ def test_host_levels_match_oracle_steps(host_lib, A):
         np.testing.assert_allclose(s2[c], s_ref, rtol=1e-5, atol=1e-6)
         want = float(r1[c // A]) + gamma * r_ref
         assert abs(r2[c] - want) <= 1e-5 * max(1.0, abs(want))
+    host_lib.shim_free(m)
+
+
+@pytest.mark.parametrize("A", [2, 10])
+def test_host_search_matches_oracle(host_lib, A):
+    """The CPU BFS (levels, leaf values r + gamma^d max Q, block maxima, Q0
+    and the Eq. 3 shift) against the FP64 depth-first oracle."""
+    from oracle import search as S
+    w = W.mlp_weights(11, A)
+    m = host_lib.shim_create(A, _p(_dev_blob(w)))
+    w64 = M.prepare(w)
+    gamma, n = 0.97, 3
+    roots = _f(W.mlp_states(13, n))
+    for d in range(0, 6 if A == 2 else 4):
+        for corr in (True, False):
+            pe = S.penalty(1.0, 0.0, A, d) if corr and d >= 1 else 0.0      # B = pe d_e - po d_o (Eq. 6)
+            po = -S.penalty(0.0, 1.0, A, d) if corr and d >= 1 else 0.0
+            act = np.zeros(n, np.int32)
+            q = np.zeros((n, A), np.float32)
+            host_lib.shim_search(m, n, _p(roots), d, np.float32(gamma), int(corr), np.float32(pe), np.float32(po),
+                                 np.float32(1.0 if corr else 0.0), act.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 _p(q))
+            for r in range(n):
+                ref = M.search(w64, roots[r].astype(np.float64), d, A, gamma, correction=corr, c=1.0)
+                qo = np.asarray(ref.q, dtype=np.float64)
+                err = np.abs(q[r].astype(np.float64) - qo).max()
+                assert err <= 1e-5 * np.abs(qo).max() + 1e-6, (A, d, corr, r, err)
+                assert act[r] == ref.action or act[r] in ref.ties, (A, d, corr, r, act[r], ref.action)
     host_lib.shim_free(m)
