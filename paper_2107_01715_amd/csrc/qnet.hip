@@ -288,7 +288,7 @@ struct LayerArgs {
   long long item_base;         // plan-global index of the chunk's first item
 };
 
-template <int L, int P>
+template <int L, int P, bool WK = false>
 __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
   typedef typename PT<P>::T T;
   constexpr int BN = Geo<L>::BN, NF = BN / 16, K = Geo<L>::K, NU = K / 8;
@@ -342,27 +342,65 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
     }
   };
 
-  // FP32 fc1 runs K in kFc1Split slices, one per blockIdx.z (see run_layer)
+  // FP32 fc1 runs K in kFc1Split slices, each summed from zero; the slices'
+  // sums are added in slice order.  Either one workgroup per slice
+  // (blockIdx.z) and fc1_reduce_kernel adds them, or (WK, for chunks with
+  // workgroups enough without the split) each workgroup runs
+  // the slices in turn and adds them in registers: the same sums in the
+  // same order, the same bits (see run_layer).
   constexpr bool kSplit = (L == 3 && P == P_FP32);
   static_assert(!kSplit || NSTAGE % kFc1Split == 0, "fc1's stages split evenly");
-  const int st0 = kSplit ? (int)blockIdx.z * (NSTAGE / kFc1Split) : 0;
-  const int st1 = kSplit ? st0 + NSTAGE / kFc1Split : NSTAGE;
-  gload(st0);
-  lstore();
-  lds_barrier();
-  for (int st = st0; st < st1; ++st) {
-    if (st + 1 < st1) gload(st + 1);
-    mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
+  constexpr bool whole_k = kSplit && WK;
+  const int nz = whole_k ? kFc1Split : 1;
+  f32x4 tot[2][NF];
+  for (int zi = 0; zi < nz; ++zi) {
+    const int z = whole_k ? zi : (int)blockIdx.z;
+    const int st0 = kSplit ? z * (NSTAGE / kFc1Split) : 0;
+    const int st1 = kSplit ? st0 + NSTAGE / kFc1Split : NSTAGE;
+    if (zi > 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    gload(st0);
+    lstore();
     lds_barrier();
-    if (st + 1 < st1) {
-      lstore();
+    for (int st = st0; st < st1; ++st) {
+      if (st + 1 < st1) gload(st + 1);
+      mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
       lds_barrier();
+      if (st + 1 < st1) {
+        lstore();
+        lds_barrier();
+      }
+    }
+    if constexpr (whole_k) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) tot[i][j] = zi == 0 ? acc[i][j] : tot[i][j] + acc[i][j];
     }
   }
 
   // epilogue: lane holds rows 4*(lane>>4) + q, column lane & 15 of each frag
   const int col = lane & 15, rq = (lane >> 4) * 4;
-  if constexpr (kSplit) {
+  if constexpr (whole_k) {
+    // h = ReLU(sum * scale + b), as fc1_reduce_kernel forms it
+    float* out = reinterpret_cast<float*>(args.out);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const int n = n0 + j * 16 + col;
+        const float b = args.bias[n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long long m = m0 + wave * 32 + i * 16 + rq + q;
+          if (m < args.M) out[m * Geo<L>::N + n] = fmaxf(fmaf(tot[i][j][q], args.acc_scale, b), 0.f);
+        }
+      }
+  } else if constexpr (kSplit) {
     // the slice's raw partial sums; fc1_reduce_kernel adds the slices in order
     float* part = args.part + (long long)blockIdx.z * args.M * Geo<L>::N;
 #pragma unroll
@@ -595,19 +633,30 @@ __global__ void fc1_reduce_kernel(long long M, const float* __restrict__ part, c
   if (t >= M * 512) return;
   float v = part[t];
   for (int z = 1; z < kFc1Split; ++z) v += part[z * M * 512 + t];
-  out[t] = fmaxf(v * scale + bias[t % 512], 0.f);
+  out[t] = fmaxf(fmaf(v, scale, bias[t % 512]), 0.f);
 }
 
-// FP32 fc1 (K = 3136, 98 stages) splits K into kFc1Split slices, each its
-// own workgroup, then sums the slices in a fixed order: a small batch (the
-// correction's FP32 evaluations of a few roots) then runs 7x more
-// workgroups instead of one long serial K loop, and every row's sum order
-// stays fixed whatever the batch.
+// FP32 fc1 (K = 3136, 98 stages) splits K into kFc1Split slices summed in a
+// fixed order, so that every row's sum order stays fixed whatever the
+// batch.  A small batch (the correction's FP32 evaluations of a few roots)
+// runs each slice as its own workgroup, 7x more workgroups than one long
+// serial K loop, and a second kernel adds the slices; a chunk that fills
+// the GPU without that runs all slices in each workgroup and adds them in
+// registers, sparing the partial sums' round trip through HBM.
 template <int L, int P>
 void run_layer(const LayerArgs& a, hipStream_t s) {
   const long long blocks = (a.M + kBM - 1) / kBM;
-  constexpr bool split = (L == 3 && P == P_FP32);
+  constexpr bool split_k = (L == 3 && P == P_FP32);
+  // slices as workgroups only while the chunk's own workgroups (4 per 128
+  // stacks) fall short of about two per CU
+  const bool split = split_k && blocks * (Geo<L>::N / Geo<L>::BN) < 512;
   dim3 grid((unsigned)blocks, Geo<L>::N / Geo<L>::BN, split ? kFc1Split : 1);
+  if constexpr (split_k) {
+    if (!split) {
+      hipLaunchKernelGGL((layer_kernel<L, P, true>), grid, dim3(kThreads), 0, s, a);
+      return;
+    }
+  }
   hipLaunchKernelGGL((layer_kernel<L, P>), grid, dim3(kThreads), 0, s, a);
   if (split) {
     const long long t = a.M * 512;
