@@ -19,6 +19,8 @@
 // (v_mfma_f32_16x16x32_bf16) or OCP e4m3 (v_mfma_f32_16x16x32_fp8_fp8), all
 // accumulating in FP32.  The 1/255 input scaling is applied to conv1's
 // accumulator; FP8 layers rescale by 1/(input scale * weight scale).
+#include <type_traits>
+
 #include "bcts_internal.h"
 #include "qnet_groups.h"
 
@@ -459,6 +461,57 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
   }
 }
 
+// One 32-K stage of MFMAs for a wavefront's 32 x (16 NF) slice of conv1
+// with the A operand as raw pixel bytes (row stride kS8 bytes), converted
+// to the operand type as it is read: the same operand values as mma_stage
+// on a converted tile, in a quarter of the LDS (FP32).
+constexpr int kS8 = 40;        // bytes per pixel row of a stage: 32 + 8 against bank conflicts
+template <int P, int NF>
+__device__ __forceinline__ void mma_stage_pix(const uint8_t* A8, const typename PT<P>::T* Bs, int lane, float s8,
+                                              f32x4 (&acc)[2][NF]) {
+  constexpr int S = Lds<P>::S;
+  const int r = lane & 15, g = lane >> 4;
+  if constexpr (P == P_FP32) {
+    // FP32 rows are stored by lane group: bytes 8g .. 8g + 7 hold K values
+    // 4 ks + g, ks = 0..7, the values lane group g feeds the 8 MFMA steps
+    uint2 w[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) w[i] = *reinterpret_cast<const uint2*>(A8 + (i * 16 + r) * kS8 + g * 8);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      float a[2], b[NF];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = (float)(((ks < 4 ? w[i].x : w[i].y) >> (8 * (ks & 3))) & 255u);
+#pragma unroll
+      for (int j = 0; j < NF; ++j) b[j] = Bs[(j * 16 + r) * S + ks * 4 + g];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  } else {
+    typename std::conditional<P == P_BF16, bf16x8, long>::type a[2], b[NF];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const uint2 w = *reinterpret_cast<const uint2*>(A8 + (i * 16 + r) * kS8 + g * 8);
+      const Unit<P> u = pix_cvt<P>(w.x, w.y, s8);
+      __builtin_memcpy(&a[i], &u, sizeof(a[i]));
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) __builtin_memcpy(&b[j], Bs + (j * 16 + r) * S + g * 8, sizeof(b[j]));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        if constexpr (P == P_BF16)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        else
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+  }
+}
+
 // conv1 over sibling groups.  The stacks of a group (the A children of one
 // node in Alg. 1's leaf level, the A depth-1 nodes of a root) hold the same
 // channels 0..2, so conv1's sum over them, K units 0..23 (stages 0..5), is
@@ -467,15 +520,17 @@ __global__ void __launch_bounds__(kThreads) layer_kernel(LayerArgs args) {
 // stages once, then for each sibling adds channel 3 (stages 6 and 7) to a
 // copy of that partial sum and stores the sibling's rows.  Every output sees
 // the MFMAs of layer_kernel<0, P> in the same order, so the two agree bit
-// for bit; the work per group of A falls from 8A stages to 6 + 2A.
+// for bit; the work per group of A falls from 8A stages to 6 + 2A.  The
+// pixel tiles hold raw bytes (converted as the MFMAs read them) and are
+// double-buffered: one barrier per stage.
 template <int P>
 __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) {
   typedef typename PT<P>::T T;
   constexpr int S = Lds<P>::S, N = Geo<0>::N, NF = N / 16, K = Geo<0>::K, PIX = Geo<0>::MPI;
   constexpr int kShared = 6;                    // stages over channels 0..2
   static_assert(Geo<0>::BN == N && K == 8 * kBKU * 8, "conv1: one column tile, 8 stages");
-  __shared__ __attribute__((aligned(16))) T As[kBM * S];
-  __shared__ __attribute__((aligned(16))) T Bs[N * S];         // the shared stages' weights, streamed
+  __shared__ __attribute__((aligned(16))) uint8_t A8[2][kBM * kS8];   // pixel bytes, double-buffered
+  __shared__ __attribute__((aligned(16))) T Bs[2][N * S];      // the shared stages' weights, double-buffered
   __shared__ __attribute__((aligned(16))) T Bo[2][N * S];      // channel 3's two stages, resident
   __shared__ const uint8_t* own[2][kMaxA];                     // each sibling's channel-3 frame
   __shared__ const uint8_t* shf[2][3];                         // the two groups' channels 0..2
@@ -522,18 +577,17 @@ __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) 
     const int pix = m - (g_lo + hr[k]) * PIX;
     off[k] = m < M ? (pix / 20) * 4 * kFrame + (pix % 20) * 4 : -1;
   }
-  unsigned raw[2][2];
+  uint2 raw[2];
   Unit<P> gb;
   // shared stage t: channel t / 2 of the row's group, rows kh = 4 (t % 2) + ua
   auto load_shared = [&](int t) {
     const int U = t * kBKU + ua, c = U >> 3, kh = U & 7;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      raw[k][0] = raw[k][1] = 0u;
+      raw[k] = make_uint2(0u, 0u);
       if (off[k] >= 0) {
         const uint8_t* q = shf[hr[k]][c] + off[k] + kh * kFrame;
-        raw[k][0] = *reinterpret_cast<const unsigned*>(q);
-        raw[k][1] = *reinterpret_cast<const unsigned*>(q + 4);
+        raw[k] = make_uint2(*reinterpret_cast<const unsigned*>(q), *reinterpret_cast<const unsigned*>(q + 4));
       }
     }
     if (tid < N * kBKU) gb = load_unit<P>(W + (long long)(tid >> 2) * K + (t * kBKU + (tid & 3)) * 8);
@@ -543,22 +597,35 @@ __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) 
     const int kh = hf * kBKU + ua;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      raw[k][0] = raw[k][1] = 0u;
+      raw[k] = make_uint2(0u, 0u);
       const uint8_t* f = own[hr[k]][sb];
       if (off[k] >= 0 && f) {                   // else past M or past the row's group
         const uint8_t* q = f + off[k] + kh * kFrame;
-        raw[k][0] = *reinterpret_cast<const unsigned*>(q);
-        raw[k][1] = *reinterpret_cast<const unsigned*>(q + 4);
+        raw[k] = make_uint2(*reinterpret_cast<const unsigned*>(q), *reinterpret_cast<const unsigned*>(q + 4));
       }
     }
   };
-  auto store_a = [&]() {
+  auto store_a = [&](int buf) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) st_unit<P>(As + (ra + 64 * k) * S, ua, pix_cvt<P>(raw[k][0], raw[k][1], args.in_s8));
+    for (int k = 0; k < 2; ++k) {
+      uint8_t* row = &A8[buf][(ra + 64 * k) * kS8];
+      if constexpr (P == P_FP32) {
+        // K value 8 ua + e goes to lane group e % 4, step 2 ua + e / 4
+        const unsigned lo = __builtin_amdgcn_perm(raw[k].y, raw[k].x, 0x05010400u);   // x0 y0 x1 y1
+        const unsigned hi = __builtin_amdgcn_perm(raw[k].y, raw[k].x, 0x07030602u);   // x2 y2 x3 y3
+        *reinterpret_cast<uint16_t*>(row + 0 * 8 + 2 * ua) = (uint16_t)lo;
+        *reinterpret_cast<uint16_t*>(row + 1 * 8 + 2 * ua) = (uint16_t)(lo >> 16);
+        *reinterpret_cast<uint16_t*>(row + 2 * 8 + 2 * ua) = (uint16_t)hi;
+        *reinterpret_cast<uint16_t*>(row + 3 * 8 + 2 * ua) = (uint16_t)(hi >> 16);
+      } else {
+        *reinterpret_cast<uint2*>(row + ua * 8) = raw[k];
+      }
+    }
   };
-  auto store_b = [&]() {
-    if (tid < N * kBKU) st_unit<P>(Bs + (tid >> 2) * S, tid & 3, gb);
+  auto store_b = [&](int buf) {
+    if (tid < N * kBKU) st_unit<P>(Bs[buf] + (tid >> 2) * S, tid & 3, gb);
   };
+  const uint8_t* Aw[2] = {A8[0] + wave * 32 * kS8, A8[1] + wave * 32 * kS8};
 
   f32x4 acc[2][NF], part[2][NF];
 #pragma unroll
@@ -566,18 +633,18 @@ __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) 
 #pragma unroll
     for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // shared stages
+  // shared stages: stage t in buffer t % 2; a buffer is refilled only after
+  // the barrier that follows every wavefront's reads of it
   load_shared(0);
-  store_a();
-  store_b();
+  store_a(0);
+  store_b(0);
   lds_barrier();
   for (int t = 0; t < kShared; ++t) {
     if (t + 1 < kShared) load_shared(t + 1);
     else load_own(0, 0);
-    mma_stage<P, NF>(As + wave * 32 * S, Bs, lane, acc);
-    lds_barrier();
-    store_a();
-    if (t + 1 < kShared) store_b();
+    mma_stage_pix<P, NF>(Aw[t & 1], Bs[t & 1], lane, args.in_s8, acc);
+    store_a((t + 1) & 1);
+    if (t + 1 < kShared) store_b((t + 1) & 1);
     lds_barrier();
   }
 #pragma unroll
@@ -585,20 +652,20 @@ __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) 
 #pragma unroll
     for (int j = 0; j < NF; ++j) part[i][j] = acc[i][j];
 
-  // siblings: channel 3 on a copy of the partial sum, then the sibling's rows.
+  // siblings: channel 3 (stages 6 and 7, buffers 0 and 1) on a copy of the
+  // partial sum, then the sibling's rows.
   // Row index of the output: item * 400 + pix = m + (i_h - g_h) * 400.
   const int col = lane & 15, rq = (lane >> 4) * 4;
   const int d_lo = (i_lo - g_lo) * PIX, d_hi = (i_hi - g_lo - 1) * PIX;
   T* out = reinterpret_cast<T*>(args.out);
   for (int sb = 0; sb < smax; ++sb) {
     load_own(sb, 1);
-    mma_stage<P, NF>(As + wave * 32 * S, Bo[0], lane, acc);
-    lds_barrier();
-    store_a();
+    mma_stage_pix<P, NF>(Aw[0], Bo[0], lane, args.in_s8, acc);
+    store_a(1);
     lds_barrier();
     const bool more = sb + 1 < smax;
     if (more) load_own(sb + 1, 0);
-    mma_stage<P, NF>(As + wave * 32 * S, Bo[1], lane, acc);
+    mma_stage_pix<P, NF>(Aw[1], Bo[1], lane, args.in_s8, acc);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -618,11 +685,8 @@ __global__ void __launch_bounds__(kThreads) conv1_groups_kernel(LayerArgs args) 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < NF; ++j) acc[i][j] = part[i][j];
+    if (more) store_a(0);
     lds_barrier();
-    if (more) {
-      store_a();
-      lds_barrier();
-    }
   }
 }
 

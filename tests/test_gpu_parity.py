@@ -114,7 +114,8 @@ def test_fp32_sibling_groups_match_oracle(lib, setup):
 def test_conv1_groups_searches_bit_identical(lib, setup):
     """Whole searches with conv1 by sibling groups equal those with conv1 per
     stack, bit for bit: FP32 (every layer-path chunk), BF16 (its FP32
-    correction evaluations, groups of A depth-1 nodes and single roots),
+    correction evaluations, groups of A depth-1 nodes and single roots), BF16
+    and FP8 with fusion off (their leaves through the group kernel too),
     on a mixed batch with A in {4, 6, 18}, d in {1, 2, 3}, in small chunks
     so that groups end at chunk edges; the default per-chunk choice (which
     here takes both kernels) agrees with both."""
@@ -134,10 +135,21 @@ def test_conv1_groups_searches_bit_identical(lib, setup):
             for k in (1, 2):
                 assert np.array_equal(out[0][0], out[k][0]), (prec, k)
                 assert np.array_equal(out[0][1], out[k][1]), (prec, k)
+        # BF16 and FP8 with fusion off: their leaves on the layer path too
+        ctx.set_tuning(lib.TUNE_FUSED, 0)
+        for prec in (lib.BF16, lib.FP8):
+            ctx.set_precision(prec)
+            out = []
+            for knob in (2, 0):
+                ctx.set_tuning(lib.TUNE_CONV1_GROUPS, knob)
+                out.append(ctx.search_batch(pos, st, d, A, GAMMA, corr))
+            assert np.array_equal(out[0][0], out[1][0]), prec
+            assert np.array_equal(out[0][1], out[1][1]), prec
         with pytest.raises(lib.BctsError) as e:
             ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 3)
         assert e.value.status == lib.E_INVAL
     finally:
+        ctx.set_tuning(lib.TUNE_FUSED, 1)
         ctx.set_tuning(lib.TUNE_CONV1_GROUPS, 1)
         ctx.set_tuning(lib.TUNE_LAYER_CHUNK, chunk)
         ctx.set_precision(lib.FP32)
