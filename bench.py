@@ -782,6 +782,9 @@ def main():
         kernels[name] = {"ms_per_step": ms, "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                          "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else None,
                          "algorithmic_flop_per_stack": flops_of[name]}
+        if name == "fc2" and fused:
+            kernels[name]["note"] = ("fc2's matrix work runs in fc1's epilogue (BCTS_TUNE_FC2_FOLDED); this is the "
+                                     "kernel that adds its two halves and writes V and the q0 rows")
         if name == "conv1" and kern[20] > 0 and kern[20] == launches and ms > 0:
             # every chunk's conv1 ran by sibling groups: the 6 stages of the
             # shared channels once per group of A, 2 per stack (of 8)

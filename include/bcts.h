@@ -273,7 +273,15 @@ void bcts_graph_destroy(bcts_graph* graph);
  *                          for small trees (at most 32 + 9 d nodes per
  *                          root, where one host core beats a host-buffer
  *                          GPU search), the GPU otherwise.  0 (default) =
- *                          the GPU (with BCTS_TUNE_MLP_CROSSOVER).          */
+ *                          the GPU (with BCTS_TUNE_MLP_CROSSOVER).
+ *   BCTS_TUNE_FC2_FOLDED   BF16/FP8 fused path: 1 (default) = fc2 runs in
+ *                          fc1's epilogue on the fc1 outputs rounded to the
+ *                          operand type, each half of fc1's 512 outputs
+ *                          summed apart and the halves added in a fixed
+ *                          order; 0 = fc1 writes those outputs to device
+ *                          memory and fc2 reads them back.  The same
+ *                          operands, the sum over the 512 associated
+ *                          differently: results agree to FP32 rounding.    */
 typedef enum {
   BCTS_TUNE_FUSED = 0,
   BCTS_TUNE_FUSED_ROUND = 1,
@@ -283,7 +291,8 @@ typedef enum {
   BCTS_TUNE_MLP_CROSSOVER = 5,
   BCTS_TUNE_FP8_K128 = 6,
   BCTS_TUNE_CONV1_GROUPS = 7,
-  BCTS_TUNE_MLP_HOST = 8
+  BCTS_TUNE_MLP_HOST = 8,
+  BCTS_TUNE_FC2_FOLDED = 9
 } bcts_tune_key;
 bcts_status bcts_set_tuning(bcts_ctx* ctx, int32_t key, int64_t value);
 bcts_status bcts_get_tuning(bcts_ctx* ctx, int32_t key, int64_t* value);

@@ -49,6 +49,7 @@ TUNE_FUSED, TUNE_FUSED_ROUND, TUNE_FUSED_CHUNK, TUNE_LAYER_CHUNK, TUNE_CORR_FP32
 TUNE_FP8_K128 = 6
 TUNE_CONV1_GROUPS = 7
 TUNE_MLP_HOST = 8
+TUNE_FC2_FOLDED = 9
 
 
 class EnvParamsC(ctypes.Structure):

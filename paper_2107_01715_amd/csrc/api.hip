@@ -57,6 +57,7 @@ struct bcts_ctx {
   int fused_T = 3;                      // items per LDS round of the fused conv kernel
   bool fp8_k128 = true;                 // FP8 conv2 / conv3 on the K = 128 matrix instruction
   int conv1_groups = 1;                 // layer path, conv1 by sibling groups: 0 never, 1 when faster, 2 always
+  bool fc2_folded = true;               // fused path: fc2 in fc1's epilogue (else fc1 writes h)
   bool fused = true;
   bool corr_fp32 = true;                // root / depth-1 evals of corrected roots in FP32
   int beam = 0;                         // pruned search: nodes kept per root action at cut levels (0: none)
@@ -405,7 +406,7 @@ bcts_status enqueue_qnet_chunk(bcts_ctx* c, const Plan& p, char* A, ItemDesc* de
     HIPCHECK(c, hipEventRecord(cev[2], s));
     HIPCHECK(c, hipEventRecord(cev[3], s));
   }
-  launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr);
+  launch_qnet_fc(c->prec, q, desc, cnt, x3, h, V + ch.i0, q0, s, cev ? cev[4] : nullptr, c->fc2_folded);
   if (cev) HIPCHECK(c, hipEventRecord(cev[5], s));
   return BCTS_OK;
 }
@@ -1789,6 +1790,9 @@ bcts_status bcts_set_tuning(bcts_ctx* c, int32_t key, int64_t value) {
     case BCTS_TUNE_CORR_FP32:
       c->corr_fp32 = value != 0;
       return BCTS_OK;
+    case BCTS_TUNE_FC2_FOLDED:
+      c->fc2_folded = value != 0;
+      return BCTS_OK;
     case BCTS_TUNE_MLP_HOST:
       if (value < 0 || value > 2) return fail(c, BCTS_E_INVAL, "host search mode must be 0, 1 or 2");
       c->mlp_host = (int)value;
@@ -1814,6 +1818,7 @@ bcts_status bcts_get_tuning(bcts_ctx* c, int32_t key, int64_t* value) {
     case BCTS_TUNE_FP8_K128: *value = c->fp8_k128 ? 1 : 0; return BCTS_OK;
     case BCTS_TUNE_CONV1_GROUPS: *value = c->conv1_groups; return BCTS_OK;
     case BCTS_TUNE_MLP_HOST: *value = c->mlp_host; return BCTS_OK;
+    case BCTS_TUNE_FC2_FOLDED: *value = c->fc2_folded ? 1 : 0; return BCTS_OK;
     default: return fail(c, BCTS_E_INVAL, "unknown tuning key %d", key);
   }
 }

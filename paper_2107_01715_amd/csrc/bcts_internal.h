@@ -115,12 +115,28 @@ void launch_fc1_weight_tiles(const void* src, void* dst, int N, int K, int eb, h
 void launch_fc1_mfma(int prec, long long n, const void* x3, const void* w, const float* bias, float acc_scale,
                      float out_s8, void* h, hipStream_t s);
 
+// fc1 with fc2 folded into its epilogue (BF16 / FP8; w2 [32][512] in the
+// operand type, bias b2, accumulator scale scale2): fc2 takes the fc1
+// outputs rounded to the operand type, as launch_fc1_mfma stores them; each
+// fc1 workgroup sums fc2 over its 256 neurons into part [2][n][32] FP32 (256
+// bytes per stack, device memory the caller owns), then a second kernel adds
+// the two halves in order and writes V[item] = max over the item's A actions
+// and the q0 rows of root items.  The sum over the 512 neurons is associated
+// as (0..127 + 128..255) + (256..383 + 384..511).  With ev_after_fc1 an event
+// is recorded between the two launches.
+void launch_fc12(int prec, long long n, const void* x3, const void* w1, const float* b1, float scale1, float out_s8,
+                 const void* w2, float* part, hipStream_t s, hipEvent_t ev_after_fc1, const float* b2, float scale2,
+                 const ItemDesc* desc, float* V, float* q0);
+
 // fc1 (+ReLU) and fc2 (+max over A, root rows of Q_0) over a chunk whose
 // conv3 output x3 is ready (BF16 / FP8, from the fused kernel, in fc1's
-// stage-major tiles); `h` holds [n][512] in the operand type.
+// stage-major tiles).  `h` is [n][512] in the operand type: fc1's output
+// when fc2 reads it back (fc2_folded false), the room for launch_fc12's
+// partial sums otherwise.  The two forms differ only in how fc2's sum is
+// associated.
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n_items,
                     const void* x3, void* h, float* V, float* q0, hipStream_t s,
-                    hipEvent_t ev_after_fc1 = nullptr);
+                    hipEvent_t ev_after_fc1, bool fc2_folded);
 
 // ---- launchers (each in the TU that defines its kernels) ----------------
 void launch_expand(int k, long long n_nodes, LevelRoots lr, const RootInfo* roots,

@@ -1,7 +1,9 @@
 // fc1 of the Nature-DQN on the matrix cores: H = ReLU(X W^T + b) with
 // X [n][3136] (conv3 output, channels-last) and W [512][3136] (rows re-laid
 // out to the same (h, w, c) order), BF16 or OCP e4m3 operands, FP32
-// accumulate.  H [n][512] in the operand type feeds fc2.
+// accumulate.  H [n][512] in the operand type feeds fc2, or (the default
+// form, FC2) fc2 runs in the epilogue on the same rounded values and H is
+// never written.
 //
 // A workgroup of 8 wavefronts computes a 256 (stacks) x 256 (neurons) tile:
 // wave (wm, wn) owns 64 x 128, i.e. 4 x 8 MFMA 16x16x32 fragments, so one
@@ -77,14 +79,15 @@ template <> struct FT<P_BF16> {
     const bf16x2 h1 = __builtin_convertvector(f32x2{c, d}, bf16x2);
     *reinterpret_cast<uint2*>(p) = make_uint2(__builtin_bit_cast(unsigned, h0), __builtin_bit_cast(unsigned, h1));
   }
-  // 8 consecutive neurons -> 16 bytes
-  __device__ static void st8(void* p, const float (&v)[8], float) {
+  // 8 consecutive neurons -> one operand (16 bytes)
+  __device__ static V pack8(const float (&v)[8], float) {
     unsigned w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       w[k] = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{v[2 * k], v[2 * k + 1]}, bf16x2));
-    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+    return __builtin_bit_cast(V, make_uint4(w[0], w[1], w[2], w[3]));
   }
+  __device__ static void st8(void* p, const float (&v)[8], float s8) { *reinterpret_cast<V*>(p) = pack8(v, s8); }
 };
 template <> struct FT<P_FP8> {
   typedef long V;
@@ -98,7 +101,8 @@ template <> struct FT<P_FP8> {
     const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
     *reinterpret_cast<unsigned*>(p) = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
   }
-  __device__ static void st8(void* p, const float (&v)[8], float s8) {
+  // 8 consecutive neurons, scaled by s8 -> one operand (8 bytes of e4m3)
+  __device__ static V pack8(const float (&v)[8], float s8) {
     unsigned w[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -108,8 +112,9 @@ template <> struct FT<P_FP8> {
       const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
       w[k] = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], lo, true);
     }
-    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+    return __builtin_bit_cast(V, make_uint2(w[0], w[1]));
   }
+  __device__ static void st8(void* p, const float (&v)[8], float s8) { *reinterpret_cast<V*>(p) = pack8(v, s8); }
 };
 
 // byte offset of (row r, logical 16-byte chunk c) inside a stage's A or B
@@ -121,10 +126,11 @@ template <> struct FT<P_FP8> {
 template <int EB> __device__ __forceinline__ int swz_x(int r) { return EB == 1 ? ((r >> 3) & 1) : ((r >> 2) & 2); }
 template <int EB> __device__ __forceinline__ int swz(int r, int c) { return r * kRB + ((c ^ swz_x<EB>(r)) << 4); }
 
-template <int P>
+template <int P, bool FC2 = false>
 __global__ void __launch_bounds__(kThreads, 1)
 fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char* __restrict__ W,
-           const float* __restrict__ bias, float acc_scale, float out_s8, unsigned char* __restrict__ H) {
+           const float* __restrict__ bias, float acc_scale, float out_s8, unsigned char* __restrict__ H,
+           const unsigned char* __restrict__ W2, float* __restrict__ part) {
   typedef FT<P> Ft;
   typedef typename Ft::V V;
   constexpr int EB = Ft::EB;
@@ -275,6 +281,70 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
   // fragments 2k and 2k + 1 give the lane neurons n0 + wn*128 + 32k + 8g
   // + 0..7 of stack m0 + wm*64 + 16j + r16: one 16-byte (BF16) or 8-byte
   // (FP8) store
+  if constexpr (FC2) {
+    // fc2 on the wavefront's 128 neurons, 4 K steps of 32: A = fc2's weight
+    // rows (actions 16 af + r16, K values 8g .. 8g + 7 of the step), B = the
+    // lane's 8 neurons of stack 16 j + r16 in the operand type, the values h
+    // would hold: the same operands as fc2 on h, without h
+    f32x4 q2[2][4];
+#pragma unroll
+    for (int af = 0; af < 2; ++af)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) q2[af][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int nb = n0 + wn * 128 + 32 * k + 8 * g;
+      float b[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[e] = bias[nb + e];
+      V w2[2];
+#pragma unroll
+      for (int af = 0; af < 2; ++af)
+        w2[af] = *reinterpret_cast<const V*>(W2 + ((size_t)(af * 16 + r16) * 512 + nb) * EB);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[4 * h + q] = fmaxf(acc[2 * k + h][j][q] * acc_scale + b[4 * h + q], 0.f);
+        const V hv = Ft::pack8(v, out_s8);
+#pragma unroll
+        for (int af = 0; af < 2; ++af) q2[af][j] = Ft::mma(w2[af], hv, q2[af][j]);
+      }
+    }
+    // the tile's two neuron halves (wn = 0, 1) added in that order, through
+    // the ring (every wavefront has finished reading it at the barrier):
+    // element e of lane l of wave (wm, 1) at [e][wm][l]
+    float* xq = reinterpret_cast<float*>(&ring[0][0]);
+    lds_barrier();
+    if (wn == 1) {
+#pragma unroll
+      for (int af = 0; af < 2; ++af)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xq[(((af * 4 + j) * 4 + q) * 4 + wm) * 64 + lane] = q2[af][j][q];
+    }
+    lds_barrier();
+    if (wn == 0) {
+      // part[half][stack][32]: this tile's sum over its 256 neurons; lane
+      // holds actions 16 af + 4g + q of stack m0 + wm*64 + 16j + r16
+      float* P2 = part + (size_t)(slot & 1) * n * 32;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long long m = m0 + wm * 64 + 16 * j + r16;
+#pragma unroll
+        for (int af = 0; af < 2; ++af) {
+          f32x4 t;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t[q] = q2[af][j][q] + xq[(((af * 4 + j) * 4 + q) * 4 + wm) * 64 + lane];
+          if (m < n) *reinterpret_cast<f32x4*>(P2 + m * 32 + 16 * af + 4 * g) = t;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int nb = n0 + wn * 128 + 32 * k + 8 * g;
@@ -294,6 +364,27 @@ fc1_kernel(long long n, const unsigned char* __restrict__ X, const unsigned char
       }
     }
   }
+}
+
+// fc2 after fc1_kernel<P, true>: Q[a] = (part_0[a] + part_1[a]) * scale
+// + b[a] (the two neuron halves in order); V = max over the stack's A
+// actions; a root item's q0 row.  Two stacks per wavefront, lane = action.
+__global__ void __launch_bounds__(256) fc2_sum_kernel(long long n, const float* __restrict__ part,
+                                                      const float* __restrict__ bias, float scale,
+                                                      const ItemDesc* __restrict__ desc, float* __restrict__ V,
+                                                      float* __restrict__ q0) {
+  const long long m = (long long)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int a = threadIdx.x & 31;
+  const bool in = m < n;
+  const long long mm = in ? m : 0;
+  const float qv = fmaf(part[mm * 32 + a] + part[(n + mm) * 32 + a], scale, a < kMaxA ? bias[a] : 0.f);
+  const ItemDesc d = desc[mm];
+  float v = a < d.A ? qv : -INFINITY;
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if (!in) return;
+  if (a == 0) V[m] = v;
+  if (d.q0_root >= 0 && a < kMaxA) q0[(long long)d.q0_root * kMaxA + a] = qv;
 }
 
 // one thread per 16 bytes of W[N][K]
@@ -328,8 +419,27 @@ void launch_fc1_mfma(int prec, long long n, const void* x3, const void* w, const
   const unsigned char* X = reinterpret_cast<const unsigned char*>(x3);
   const unsigned char* Wp = reinterpret_cast<const unsigned char*>(w);
   unsigned char* H = reinterpret_cast<unsigned char*>(h);
-  if (prec == P_BF16) hipLaunchKernelGGL((fc1_kernel<P_BF16>), grid, block, 0, s, n, X, Wp, bias, acc_scale, out_s8, H);
-  else hipLaunchKernelGGL((fc1_kernel<P_FP8>), grid, block, 0, s, n, X, Wp, bias, acc_scale, out_s8, H);
+  if (prec == P_BF16)
+    hipLaunchKernelGGL((fc1_kernel<P_BF16>), grid, block, 0, s, n, X, Wp, bias, acc_scale, out_s8, H, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((fc1_kernel<P_FP8>), grid, block, 0, s, n, X, Wp, bias, acc_scale, out_s8, H, nullptr, nullptr);
+}
+
+void launch_fc12(int prec, long long n, const void* x3, const void* w1, const float* b1, float scale1, float out_s8,
+                 const void* w2, float* part, hipStream_t s, hipEvent_t ev_after_fc1, const float* b2, float scale2,
+                 const ItemDesc* desc, float* V, float* q0) {
+  if (n <= 0) return;
+  const long long mtiles = ((n + kBM - 1) / kBM + 7) / 8 * 8;
+  dim3 grid((unsigned)(mtiles * (512 / kBN))), block(kThreads);
+  const unsigned char* X = reinterpret_cast<const unsigned char*>(x3);
+  const unsigned char* W1 = reinterpret_cast<const unsigned char*>(w1);
+  const unsigned char* W2 = reinterpret_cast<const unsigned char*>(w2);
+  if (prec == P_BF16)
+    hipLaunchKernelGGL((fc1_kernel<P_BF16, true>), grid, block, 0, s, n, X, W1, b1, scale1, out_s8, nullptr, W2, part);
+  else
+    hipLaunchKernelGGL((fc1_kernel<P_FP8, true>), grid, block, 0, s, n, X, W1, b1, scale1, out_s8, nullptr, W2, part);
+  if (ev_after_fc1) (void)hipEventRecord(ev_after_fc1, s);
+  hipLaunchKernelGGL(fc2_sum_kernel, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, s, n, part, b2, scale2, desc, V, q0);
 }
 
 }  // namespace bcts

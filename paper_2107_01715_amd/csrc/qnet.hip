@@ -817,21 +817,27 @@ void run_qnet(const QnetDev& q, const ItemDesc* desc, long long n, const ChunkGr
   if (ev) (void)hipEventRecord(ev[5], s);
 }
 
+// fc1 and fc2 after the fused conv kernel: with `folded` fc2 runs in fc1's
+// epilogue (its partial sums take h's place in the workspace), else fc1
+// writes h and fc2 + max reads it
 template <int P>
 void run_fc(const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h, float* V, float* q0,
-            hipStream_t s, hipEvent_t ev) {
-  auto wp = [&](int l) -> const void* {
-    return P == P_FP32 ? (const void*)q.w[l] : P == P_BF16 ? (const void*)q.wb[l] : (const void*)q.w8[l];
-  };
+            hipStream_t s, hipEvent_t ev, bool folded) {
+  static_assert(P != P_FP32, "x3 comes from the fused kernel (BF16 / FP8), in stage-major tiles");
   auto accs = [&](int l) { return (P == P_FP8) ? 1.f / (q.ascale[l] * q.wscale[l]) : 1.f; };
+  const void* w1 = P == P_BF16 ? (const void*)q.wfb[3] : (const void*)q.wf8[3];
+  const void* w2 = P == P_BF16 ? (const void*)q.wb[4] : (const void*)q.w8[4];
+  const float out_s8 = P == P_FP8 ? q.ascale[4] : 1.f;
+  if (folded) {
+    launch_fc12(P, n, x3, w1, q.b[3], accs(3), out_s8, w2, reinterpret_cast<float*>(h), s, ev, q.b[4], accs(4), desc,
+                V, q0);
+    return;
+  }
+  launch_fc1_mfma(P, n, x3, w1, q.b[3], accs(3), out_s8, h, s);
+  if (ev) (void)hipEventRecord(ev, s);
   LayerArgs a{};
   a.desc = desc;
-  a.M = n; a.in = x3; a.w = wp(3); a.bias = q.b[3]; a.acc_scale = accs(3);
-  a.out_s8 = P == P_FP8 ? q.ascale[4] : 1.f; a.out = h;
-  static_assert(P != P_FP32, "x3 comes from the fused kernel (BF16 / FP8), in stage-major tiles");
-  launch_fc1_mfma(P, n, x3, P == P_BF16 ? q.wfb[3] : q.wf8[3], q.b[3], accs(3), a.out_s8, h, s);
-  if (ev) (void)hipEventRecord(ev, s);
-  a.M = n; a.in = h; a.w = wp(4); a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
+  a.M = n; a.in = h; a.w = w2; a.bias = q.b[4]; a.acc_scale = accs(4); a.out = nullptr; a.V = V; a.q0 = q0;
   run_layer<4, P>(a, s);
 }
 
@@ -875,10 +881,10 @@ void launch_qnet_groups(int prec, const QnetDev& q, const ItemDesc* desc, long l
 }
 
 void launch_qnet_fc(int prec, const QnetDev& q, const ItemDesc* desc, long long n, const void* x3, void* h,
-                    float* V, float* q0, hipStream_t s, hipEvent_t ev) {
+                    float* V, float* q0, hipStream_t s, hipEvent_t ev, bool folded) {
   if (n <= 0) return;
-  if (prec == P_BF16) run_fc<P_BF16>(q, desc, n, x3, h, V, q0, s, ev);
-  else run_fc<P_FP8>(q, desc, n, x3, h, V, q0, s, ev);
+  if (prec == P_BF16) run_fc<P_BF16>(q, desc, n, x3, h, V, q0, s, ev, folded);
+  else run_fc<P_FP8>(q, desc, n, x3, h, V, q0, s, ev, folded);
 }
 
 void launch_convert_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) {

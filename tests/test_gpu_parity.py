@@ -339,6 +339,38 @@ def test_fused_matches_layer_path(lib, setup):
     assert (a0 == a1).mean() >= 11 / 12
 
 
+@pytest.mark.parametrize("prec_name", ["BF16", "FP8"])
+def test_fc2_folded_matches_fc2_on_h(lib, setup, prec_name):
+    """fc2 in fc1's epilogue (the default) against fc1 writing h and fc2
+    reading it back: the same operands (fc1's outputs rounded to the operand
+    type), only fc2's FP32 sum associated differently, so the root vectors
+    agree to FP32 rounding (1e-5 of each root's largest |Q|) and the actions
+    agree except between values that close; a mixed batch with root rows of
+    Q_0 (depth 0) and leaf chunks of several sizes."""
+    ctx, _, _ = setup
+    A, d = W.mixed_shapes(1007, 60, (4, 6, 18), (0, 1, 2, 3))
+    pos, st = W.roots(1007, 60)
+    corr = lib.correction(True, 1.0)
+    chunk = ctx.get_tuning(lib.TUNE_FUSED_CHUNK)
+    try:
+        ctx.set_precision(getattr(lib, prec_name))
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, 5000)
+        out = []
+        for folded in (1, 0):
+            ctx.set_tuning(lib.TUNE_FC2_FOLDED, folded)
+            out.append(ctx.search_batch(pos, st, d, A, GAMMA, corr))
+        (a1, q1), (a0, q0) = out
+        for r in range(len(A)):
+            qa, qb = q1[r, :A[r]].astype(np.float64), q0[r, :A[r]].astype(np.float64)
+            tol = 1e-5 * np.abs(qb).max() + 1e-7
+            assert np.abs(qa - qb).max() <= tol, (r, np.abs(qa - qb).max())
+            assert a1[r] == a0[r] or qb[a1[r]] >= qb.max() - 2 * tol, (r, a1[r], a0[r])
+    finally:
+        ctx.set_tuning(lib.TUNE_FC2_FOLDED, 1)
+        ctx.set_tuning(lib.TUNE_FUSED_CHUNK, chunk)
+        ctx.set_precision(lib.FP32)
+
+
 @pytest.mark.parametrize("prec_name,rounds", [("BF16", (1, 2, 3)), ("FP8", (1, 2, 3, 4))])
 def test_fused_rounds_and_chunks_are_bitwise_identical(lib, setup, prec_name, rounds):
     """Round size and chunking change only how stacks are grouped into
